@@ -1,0 +1,145 @@
+"""FP64 CPU oracle for the Li & Stephens all-vs-all copying model.
+
+TEST INFRASTRUCTURE. Only the tests, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package. It shares no code
+with the GPU path: the arithmetic lives in ``ls_oracle.c`` (plain C, FP64,
+built with ``-ffp-contract=off``), and this module only marshals arrays.
+
+Every function here runs one recipient HMM at a time, exactly as the paper
+writes the recursions (section 2.2, eq. fwd0/fwd1, bck0/bck1, postprob,
+distmat). See ``ls_oracle.c`` for the definitions.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ls_oracle.c")
+_LIB = os.path.join(_HERE, "libls_oracle.so")
+_lib = None
+
+EPS = 2.0 ** -52
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (no GPU code)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".{os.getpid()}.tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+               "-shared", "-pthread", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def bind(path: str):
+    """Load a compiled oracle library from ``path`` and declare its C API."""
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.lso_pass.argtypes = [P, i64, i32, i32, P, f64, P, i32, P, i32,
+                             P, P, P, P, P, P, P, P, P, i32]
+    lib.lso_pass.restype = ctypes.c_int
+    lib.lso_gradient.argtypes = [P, i64, i32, i32, P, f64, P, i32, P, P, P, P, i32]
+    lib.lso_gradient.restype = ctypes.c_int
+    lib.lso_symmetrise.argtypes = [P, i32, P]
+    lib.lso_symmetrise.restype = None
+    lib.lso_version.restype = ctypes.c_char_p
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        _lib = bind(build())
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def default_threads() -> int:
+    n = os.cpu_count() or 1
+    return max(1, min(n, int(os.environ.get("LSO_THREADS", n))))
+
+
+def run_pass(H, N, L, rho, mu, recipients, targets=(), want=("P", "E"), nthreads=None, lib=None):
+    """Forward/backward pass for each recipient.
+
+    Returns a dict with ``llf``/``llb`` (forward and backward log-likelihood,
+    shape [R]) and, for each name in ``want`` among A (alpha), B (beta), P
+    (posterior), E (half distance -log(p v eps)/2), arrays of shape [T][R][N];
+    ``logF``/``logG`` are [T][R] (log F^t, log G^t); ``status`` [R] has bit 0
+    for a forward and bit 1 for a backward zero or non-finite scale sum.
+    """
+    lib = lib or _load()
+    H = np.ascontiguousarray(H, dtype=np.uint32)
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    rec = np.ascontiguousarray(recipients, dtype=np.int32)
+    tg = np.ascontiguousarray(targets, dtype=np.int32)
+    R, T = rec.size, tg.size
+    out = {}
+    for k in ("A", "B", "P", "E"):
+        out[k] = np.empty((T, R, N)) if k in want else None
+    for k in ("logF", "logG"):
+        out[k] = np.empty((T, R)) if k in want else None
+    out["llf"] = np.empty(R)
+    out["llb"] = np.empty(R)
+    out["status"] = np.zeros(R, dtype=np.int32)
+    rc = lib.lso_pass(_ptr(H), H.shape[1], N, L, _ptr(rho), float(mu), _ptr(rec), R,
+                      _ptr(tg), T, _ptr(out["A"]), _ptr(out["B"]), _ptr(out["P"]),
+                      _ptr(out["E"]), _ptr(out["logF"]), _ptr(out["logG"]), _ptr(out["llf"]),
+                      _ptr(out["llb"]), _ptr(out["status"]), nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    return {k: v for k, v in out.items() if v is not None}
+
+
+def run_gradient(H, N, L, rho, mu, recipients, nthreads=None, lib=None):
+    """Per-recipient log-likelihood and its gradient w.r.t. rho (L-1) and mu.
+
+    Returns dict(loglik [R], grad_rho [R][L-1], grad_mu [R], status [R]).
+    Holds an L x N FP64 forward table per thread.
+    """
+    lib = lib or _load()
+    H = np.ascontiguousarray(H, dtype=np.uint32)
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    rec = np.ascontiguousarray(recipients, dtype=np.int32)
+    R = rec.size
+    g = np.zeros((R, max(L - 1, 0)))
+    gm = np.empty(R)
+    ll = np.empty(R)
+    st = np.zeros(R, dtype=np.int32)
+    rc = lib.lso_gradient(_ptr(H), H.shape[1], N, L, _ptr(rho), float(mu), _ptr(rec), R,
+                          _ptr(g) if L > 1 else None, _ptr(gm), _ptr(ll), _ptr(st),
+                          nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    return dict(loglik=ll, grad_rho=g, grad_mu=gm, status=st)
+
+
+def symmetrise(E, lib=None):
+    """D[a][b] = E[a][b] + E[b][a], D[a][a] = 0 for one N x N target."""
+    lib = lib or _load()
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    N = E.shape[0]
+    D = np.empty_like(E)
+    lib.lso_symmetrise(_ptr(E), N, _ptr(D))
+    return D
+
+
+def distances(H, N, L, rho, mu, targets, nthreads=None):
+    """Full N x N distance matrices at the targets: [T][N][N]."""
+    res = run_pass(H, N, L, rho, mu, np.arange(N, dtype=np.int32), targets, want=("E",),
+                   nthreads=nthreads)
+    return np.stack([symmetrise(res["E"][k]) for k in range(len(targets))])
+
+
+def version() -> str:
+    return _load().lso_version().decode()

@@ -1,0 +1,171 @@
+"""Independent references the oracle is pinned to.
+
+Nothing here reuses the oracle's recursions. Each helper computes a quantity
+from its mathematical definition in the paper (section 2.1: the LS HMM with
+emission eq. emission, transition eq. transition, uniform prior with zero
+self-copying):
+
+* ``enumerate_exact`` sums over every hidden path in exact rational
+  arithmetic, so the likelihood, posterior marginals and derivatives are exact.
+* ``logdomain_fb`` is the textbook forward-backward over the full transition
+  matrix with log-sum-exp, in FP64 (no scale factors at all).
+* ``raw_forward`` is the unscaled recursion (eq. raw_forward), valid while it
+  does not underflow.
+* closed forms for rho = 0 (no recombination), rho = 1 (independent sites)
+  and N = 2 (a single donor).
+"""
+
+from __future__ import annotations
+
+import itertools
+from fractions import Fraction
+
+import numpy as np
+
+
+def _theta_exact(h, l, j, i, mu):
+    return mu if h[l][j] != h[l][i] else 1 - mu
+
+
+def enumerate_exact(h, rho, mu, i):
+    """Exact P(h_i | h_-i), posterior marginals p[l][j] and the derivatives
+    d log P / d rho_l (length L-1) and d log P / d mu, by summing over all
+    (N-1)^L copying paths. ``h`` is an L x N nested list of 0/1; ``rho`` a list
+    of L-1 Fractions; ``mu`` a Fraction."""
+    L, N = len(h), len(h[0])
+    donors = [j for j in range(N) if j != i]
+    pi = Fraction(1, N - 1)
+    P = Fraction(0)
+    marg = [[Fraction(0)] * N for _ in range(L)]
+    dP_drho = [Fraction(0)] * (L - 1)
+    dP_dmu = Fraction(0)
+    for path in itertools.product(donors, repeat=L):
+        em = [_theta_exact(h, l, path[l], i, mu) for l in range(L)]
+        tr = [rho[l] * pi + (1 - rho[l]) * (1 if path[l] == path[l + 1] else 0)
+              for l in range(L - 1)]
+        prob = pi
+        for e in em:
+            prob *= e
+        for t in tr:
+            prob *= t
+        P += prob
+        for l in range(L):
+            marg[l][path[l]] += prob
+        # d prob / d rho_l: replace T_l by its derivative pi - 1{j=k}
+        for l in range(L - 1):
+            d = pi - (1 if path[l] == path[l + 1] else 0)
+            rest = pi
+            for e in em:
+                rest *= e
+            for m, t in enumerate(tr):
+                if m != l:
+                    rest *= t
+            dP_drho[l] += rest * d
+        # d prob / d mu: product rule over the emissions, d theta/d mu = +-1
+        for l in range(L):
+            d = 1 if h[l][path[l]] != h[l][i] else -1
+            rest = pi
+            for m, e in enumerate(em):
+                if m != l:
+                    rest *= e
+            for t in tr:
+                rest *= t
+            dP_dmu += rest * d
+    post = [[marg[l][j] / P for j in range(N)] for l in range(L)]
+    return dict(P=P, post=post, dlogP_drho=[d / P for d in dP_drho], dlogP_dmu=dP_dmu / P)
+
+
+def _logsumexp(a, axis=None):
+    m = np.max(a, axis=axis, keepdims=True)
+    m = np.where(np.isfinite(m), m, 0.0)
+    s = np.log(np.sum(np.exp(a - m), axis=axis, keepdims=True)) + m
+    return np.squeeze(s, axis=axis) if axis is not None else float(s.ravel()[0])
+
+
+def logdomain_fb(h01, rho, mu, i):
+    """Textbook log-domain forward-backward for recipient i over the full
+    (N-1) x (N-1) transition matrix. Returns (log P, posterior [L][N])."""
+    h01 = np.asarray(h01)
+    L, N = h01.shape
+    donors = np.array([j for j in range(N) if j != i])
+    D = donors.size
+    logpi = -np.log(N - 1)
+    mis = h01[:, donors] != h01[:, [i]]
+    logth = np.where(mis, np.log(mu), np.log1p(-mu))
+    la = np.empty((L, D))
+    la[0] = logpi + logth[0]
+    for l in range(1, L):
+        T = np.full((D, D), rho[l - 1] / (N - 1)) + np.eye(D) * (1 - rho[l - 1])
+        with np.errstate(divide="ignore"):
+            logT = np.log(T)
+        la[l] = logth[l] + _logsumexp(la[l - 1][:, None] + logT, axis=0)
+    lb = np.zeros((L, D))
+    for l in range(L - 2, -1, -1):
+        T = np.full((D, D), rho[l] / (N - 1)) + np.eye(D) * (1 - rho[l])
+        with np.errstate(divide="ignore"):
+            logT = np.log(T)
+        lb[l] = _logsumexp(logT + (logth[l + 1] + lb[l + 1])[None, :], axis=1)
+    logP = _logsumexp(la[-1])
+    post = np.zeros((L, N))
+    post[:, donors] = np.exp(la + lb - logP)
+    return logP, post
+
+
+def raw_forward(h01, rho, mu, i):
+    """Unscaled forward probabilities alpha~ (eq. raw_forward), [L][N]."""
+    h01 = np.asarray(h01)
+    L, N = h01.shape
+    pi = np.full(N, 1.0 / (N - 1))
+    pi[i] = 0.0
+    th = np.where(h01 != h01[:, [i]], mu, 1.0 - mu)
+    a = np.empty((L, N))
+    a[0] = th[0] * pi
+    for l in range(1, L):
+        F = a[l - 1].sum()
+        a[l] = th[l] * ((1 - rho[l - 1]) * a[l - 1] + rho[l - 1] * F * pi)
+    return a
+
+
+def rho0_closed_form(h01, mu, i):
+    """rho == 0: the copied donor never changes. Returns (log P, posterior
+    [N], the same at every variant)."""
+    h01 = np.asarray(h01)
+    L, N = h01.shape
+    m = (h01 != h01[:, [i]]).sum(axis=0).astype(float)
+    logw = m * np.log(mu) + (L - m) * np.log1p(-mu) - np.log(N - 1)
+    logw[i] = -np.inf
+    logP = _logsumexp(logw)
+    return logP, np.exp(logw - logP)
+
+
+def rho0_closed_form_grad(h01, mu, i):
+    """d log P / d rho_l at rho == 0, l = 0..L-2:
+    [(sum_j pi A_j)(sum_k pi B_k) - sum_j pi A_j B_j] / sum_j pi A_j B_j with
+    A_j = prod_{l' <= l} theta_j, B_j = prod_{l' > l} theta_j (log domain)."""
+    h01 = np.asarray(h01)
+    L, N = h01.shape
+    donors = [j for j in range(N) if j != i]
+    logth = np.where(h01[:, donors] != h01[:, [i]], np.log(mu), np.log1p(-mu))
+    cum = np.cumsum(logth, axis=0)
+    total = cum[-1]
+    lpi = -np.log(N - 1)
+    out = np.empty(L - 1)
+    for l in range(L - 1):
+        logA = cum[l]
+        logB = total - cum[l]
+        sa = _logsumexp(lpi + logA)
+        sb = _logsumexp(lpi + logB)
+        sab = _logsumexp(lpi + logA + logB)
+        out[l] = np.exp(sa + sb - sab) - 1.0
+    return out
+
+
+def rho1_closed_form(h01, mu, i):
+    """rho == 1: variants are independent. Returns (log P, posterior [L][N])."""
+    h01 = np.asarray(h01)
+    L, N = h01.shape
+    th = np.where(h01 != h01[:, [i]], mu, 1.0 - mu)
+    th[:, i] = 0.0
+    w = th / (N - 1)
+    s = w.sum(axis=1)
+    return float(np.log(s).sum()), w / s[:, None]

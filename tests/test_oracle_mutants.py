@@ -1,0 +1,98 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each case copies the oracle's C source, plants one mistake (a dropped term, a
+wrong sign, a wrong index, a swapped operand), compiles the copy into a
+temporary directory and checks that the exact-enumeration pins reject it.
+Nothing here touches the real oracle build. CPU only.
+"""
+
+from __future__ import annotations
+
+import os
+import subprocess
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from lsinputs import pack_haplotypes
+
+from _pins import enumerate_exact
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "ls_oracle.c")
+
+MUTANTS = {
+    "forward_drops_normalisation": ("(1.0 - r) * prev[j] / S", "(1.0 - r) * prev[j]"),
+    "forward_rho_index": ("double r = m->rho[l - 1];\n    for (int j = 0; j < m->N; ++j) {\n        if (j == i) {\n            next[j] = 0.0;",
+                          "double r = m->rho[l > 1 ? l - 2 : 0];\n    for (int j = 0; j < m->N; ++j) {\n        if (j == i) {\n            next[j] = 0.0;"),
+    "emission_swapped": ("(double)(1 - Hm) * (1.0 - 2.0 * m->mu)", "(double)(Hm) * (1.0 - 2.0 * m->mu)"),
+    "prior_keeps_self": ("return j == i ? 0.0 : 1.0 / (double)(m->N - 1);",
+                         "return 1.0 / (double)(m->N - 1);"),
+    "backward_theta_index": ("cur[j] = (1.0 - r) * next[j] * theta(m, l + 1, j, i) / g + r;",
+                             "cur[j] = (1.0 - r) * next[j] * theta(m, l, j, i) / g + r;"),
+    "backward_rho_index": ("double r = m->rho[l];", "double r = m->rho[l + 1 < m->L - 1 ? l + 1 : l];"),
+    "backward_drops_rho_term": ("/ g + r;", "/ g;"),
+    "grad_rho_sign": ("grad_rho[l - 1] = (Sg - a) /", "grad_rho[l - 1] = (a - Sg) /"),
+    "grad_rho_uses_wrong_alpha": ("const double *al = alpha + (int64_t)(l - 1) * N;",
+                                  "const double *al = alpha + (int64_t)(l) * N;"),
+    "grad_mu_sign": ("-p[j] / (1.0 - m->mu);", "p[j] / (1.0 - m->mu);"),
+    "distance_not_halved": ("return -log(q) / 2.0;", "return -log(q);"),
+    "posterior_not_normalised": ("p[j] = alpha[j] * beta[j] / Z;", "p[j] = alpha[j] * beta[j];"),
+}
+
+
+def _build_mutant(tmp_path, name, find, repl):
+    src = open(SRC).read()
+    assert src.count(find) == 1, f"mutation {name!r} does not match the oracle source exactly once"
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(find, repl))
+    so = tmp_path / f"lib{name}.so"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", "-pthread",
+                    "-o", str(so), str(path), "-lm"], check=True)
+    return oracle.bind(str(so))
+
+
+def _pins_pass(lib) -> bool:
+    """The exact-enumeration pins, as in test_oracle_pins, on two cases."""
+    cases = [(5, 4, 1, Fraction(1, 16), [3, 17, 1, 29]), (4, 3, 3, Fraction(1, 4), [9, 2, 20])]
+    for L, N, seed, mu, rnum in cases:
+        h01 = (np.random.default_rng(seed).random((L, N)) < 0.5).astype(np.uint8)
+        rho = [Fraction(k, 32) for k in rnum]
+        rf = np.array([float(r) for r in rho])
+        rec = np.arange(N, dtype=np.int32)
+        tg = np.arange(L, dtype=np.int32)
+        H = pack_haplotypes(h01)
+        res = oracle.run_pass(H, N, L, rf, float(mu), rec, tg, want=("P", "E"), nthreads=1, lib=lib)
+        gr = oracle.run_gradient(H, N, L, rf, float(mu), rec, nthreads=1, lib=lib)
+        for i in range(N):
+            ex = enumerate_exact(h01.tolist(), rho, mu, i)
+            logP = np.log(float(ex["P"]))
+            post = np.array([[float(x) for x in row] for row in ex["post"]])
+            eps = 2.0 ** -52
+            Eref = -np.log(np.maximum(post, eps)) / 2
+            Eref[:, i] = 0.0
+            ok = (abs(res["llf"][i] - logP) <= 1e-12 * abs(logP)
+                  and abs(res["llb"][i] - logP) <= 1e-12 * abs(logP)
+                  and np.allclose(res["P"][:, i, :], post, rtol=1e-11, atol=1e-15)
+                  and np.allclose(res["E"][:, i, :], Eref, rtol=1e-11, atol=1e-15)
+                  and np.allclose(gr["grad_rho"][i], [float(x) for x in ex["dlogP_drho"]],
+                                  rtol=1e-9, atol=1e-12)
+                  and abs(gr["grad_mu"][i] - float(ex["dlogP_dmu"]))
+                  <= 1e-9 * abs(float(ex["dlogP_dmu"])) + 1e-9)
+            if not ok:
+                return False
+    return True
+
+
+def test_unmutated_copy_passes(tmp_path):
+    lib = _build_mutant(tmp_path, "identity", "LSO_EPS 2.220446049250313080847e-16",
+                        "LSO_EPS 2.220446049250313080847e-16")
+    assert _pins_pass(lib)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(tmp_path, name):
+    find, repl = MUTANTS[name]
+    lib = _build_mutant(tmp_path, name, find, repl)
+    assert not _pins_pass(lib), f"pins did not catch mutant {name}"
