@@ -1,0 +1,224 @@
+/*
+ * ls.h -- C ABI of libls: the Li & Stephens all-vs-all copying model
+ * (Li & Stephens 2003, in the reformulation of Aslett & Christ, "kalis",
+ * arXiv 2212.11403) on AMD Instinct MI355X (gfx950).
+ *
+ * For every recipient haplotype i the library runs one hidden Markov model
+ * whose hidden state is the donor j != i that i copies at each variant. It
+ * propagates the scaled forward and backward recursions of the paper
+ * (section 2.2, eq. fwd0/fwd1 and bck0/bck1), decodes posterior copying
+ * probabilities (eq. postprob) and local distances (eq. distmat), and
+ * returns the per-recipient log-likelihood and its gradient with respect to
+ * the recombination probabilities and the mutation probability.
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * - Indices are 0-based. Haplotypes 0..N-1, variants 0..L-1. rho[l] is the
+ *   recombination probability between variants l and l+1, l = 0..L-2 (the
+ *   paper's rho vector of length L-1, section 3.4).
+ * - The copying prior is uniform: pi_ji = 1/(N-1) for j != i and 0 for
+ *   j == i (the default prior of section 2.1; self copying excluded).
+ * - The mutation probability mu is one scalar for all variants.
+ * - Every data pointer named "device" is device memory on the current HIP
+ *   device. Pointers named "host" are host memory. The caller allocates and
+ *   owns every buffer; the library allocates nothing and keeps no global
+ *   state.
+ * - "stream" is a hipStream_t (NULL = the legacy default stream). Calls that
+ *   take a stream only validate arguments on the host, then enqueue kernels
+ *   on that stream and return; outputs are valid once the stream has
+ *   completed. A validation error returns before anything is enqueued.
+ * - Tables are modified in place, as in the paper (section 3.6).
+ * - Numerical failure is not an error code: if a column sum of a recipient
+ *   becomes 0 or non-finite ("total underflow", appendix A.3), that
+ *   recipient's column turns NaN except the diagonal, which stays 0, and
+ *   LS_FLAG_NONFINITE is set in its status word. ls_status_check() reads the
+ *   status words back.
+ */
+#ifndef LS_H
+#define LS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LS_OK = 0,
+    LS_ERR_ARG = 1,         /* NULL pointer, value out of range, bad enum */
+    LS_ERR_SHAPE = 2,       /* sizes inconsistent with each other */
+    LS_ERR_STATE = 3,       /* table at the wrong variant or direction, or
+                               built with another model (hash mismatch) */
+    LS_ERR_UNSUPPORTED = 4, /* N too large for this precision on one GPU */
+    LS_ERR_DEVICE = 5,      /* the HIP runtime reported an error */
+    LS_ERR_WORKSPACE = 6,   /* workspace missing or too small */
+    LS_WARN_NONFINITE = 16  /* returned by ls_status_check only */
+} ls_status;
+
+/* Arithmetic of the sweep.
+ * LS_FP64: everything in double precision.
+ * LS_FP32: single-precision vectors with per-step renormalisation; column
+ *   sums reduced in FP32 lanes; the log scale factors and the
+ *   log-likelihood accumulate in FP64.
+ * LS_FP32_F16STORE: as LS_FP32 but the resident forward/backward vectors are
+ *   stored in IEEE half precision, multiplied by a fixed per-direction scale
+ *   kappa (see ls_table); arithmetic is FP32. A precision-study option. */
+typedef enum { LS_FP64 = 0, LS_FP32 = 1, LS_FP32_F16STORE = 2 } ls_precision;
+
+/* Status word flags (per recipient, device memory). */
+#define LS_FLAG_NONFINITE 1u   /* a column sum was 0, Inf or NaN */
+#define LS_FLAG_BAD_RECIPIENT 2u /* recipient index outside [0, N) */
+
+/* Maximum number of targets one ls_forward / ls_backward call can visit.
+ * Longer lists are handled by several calls: tables resume where they stop. */
+#define LS_MAX_TARGETS 256
+
+/* The model: haplotypes and parameters (cf. the kalis parameter object,
+ * section 4.1.2). Fill the input fields, then call ls_model_init. */
+typedef struct {
+    /* inputs */
+    const uint32_t *H;    /* device, [L][stride_words]: haplotype j at
+                             variant l is bit (j % 32) of word j / 32 of row l
+                             (the variant-major bit cache of section 4.1.1) */
+    int64_t stride_words; /* 32-bit words per row; >= ceil(N/32), even */
+    int32_t N;            /* haplotypes, >= 2 */
+    int32_t L;            /* variants, >= 1 */
+    const double *rho;    /* device, [L-1], each in [0, 1]; may be NULL if L == 1 */
+    double mu;            /* in [0, 1] */
+    /* set by ls_model_init */
+    uint64_t hash;        /* hash of (N, L, rho, mu); tables remember it */
+    const uint64_t *Hr;   /* device: internal row layout in the workspace */
+    int64_t hr_stride;    /* 64-bit words per internal row */
+    int32_t nf;           /* number of full 64-haplotype words: floor(N/64) */
+    int32_t reserved;
+} ls_model;
+
+/* Device bytes of the workspace ls_model_init lays the internal haplotype
+ * rows into (about 2 N L / 8 bytes). */
+size_t ls_model_workspace_bytes(int32_t N, int32_t L);
+
+/* Validates the inputs, computes the hash and builds the internal rows in
+ * `workspace` (device, >= ls_model_workspace_bytes(N, L) bytes, 256-byte
+ * aligned) on `stream`. Reads rho back to the host (synchronises the
+ * stream). The workspace must stay allocated and unchanged while the model
+ * is used. Errors: LS_ERR_ARG (NULL H/rho, N < 2, L < 1, mu or rho out of
+ * range, short stride), LS_ERR_WORKSPACE, LS_ERR_DEVICE. */
+ls_status ls_model_init(ls_model *m, void *workspace, size_t ws_bytes, void *stream);
+
+/* A forward or backward table for R recipients at one variant (cf. the
+ * kalis forward/backward table, section 4.1.3).
+ *   forward at variant l:  state[r][j] = alpha^l_{j,i} (eq. fwd0/fwd1),
+ *                          log_scale[r] = log F^l = sum_{k<=l} log S_k,
+ *                          S_k = sum_j alpha^k_j (eq. F).
+ *   backward at variant l: state[r][j] = beta^l_{j,i} (eq. bck0/bck1),
+ *                          log_scale[r] = log G^l (eq. G).
+ * with i = recipients[r]. The diagonal entry j == i is always 0.
+ * Element type of state: double (LS_FP64), float (LS_FP32) or IEEE half
+ * (LS_FP32_F16STORE). Half tables hold kappa * alpha (kappa = 2^14) or
+ * kappa * beta (kappa = 2^14 / (N-1)); the recursions and posteriors do not
+ * depend on that factor. */
+typedef struct {
+    void *state;               /* device, [R][N] */
+    double *log_scale;         /* device, [R] */
+    uint32_t *status;          /* device, [R], LS_FLAG_* bits (cleared by init) */
+    const int32_t *recipients; /* device, [R], each in [0, N) */
+    int32_t R;
+    int32_t l;                 /* current variant; -1 = not yet propagated */
+    int32_t direction;         /* 0 forward, 1 backward */
+    int32_t prec;              /* ls_precision */
+    uint64_t model_hash;       /* 0 until the first propagation */
+} ls_table;
+
+/* Resets a table to "not yet propagated" (cf. MakeForwardTable /
+ * MakeBackwardTable / ResetTable). Clears the status words on `stream`.
+ * Errors: LS_ERR_ARG. */
+ls_status ls_table_init(ls_table *t, int32_t direction, ls_precision prec, void *state,
+                        double *log_scale, uint32_t *status, const int32_t *recipients,
+                        int32_t R, void *stream);
+
+/* Copies the contents of `src` into `dst` (cf. CopyTable, section 3.6).
+ * Both must have the same direction, precision and R. Errors: LS_ERR_ARG,
+ * LS_ERR_SHAPE, LS_ERR_DEVICE. */
+ls_status ls_table_copy(ls_table *dst, const ls_table *src, int32_t N, void *stream);
+
+/* Forward (cf. Forward(fwd, pars, t), section 3.6): moves `fwd` from its
+ * current variant to t (t > fwd->l; an unpropagated table starts at variant 0
+ * and may stop there, t >= 0).
+ * targets: host, [T], strictly increasing, each in (fwd->l, t], T <= 256.
+ * At each target k the forward vector is combined with the backward vector
+ * bsnap[k] (eq. postprob) and, for the outputs that are not NULL:
+ *   P[k][r][j] = p_{j,i}                         posterior (eq. postprob)
+ *   E[k][r][j] = -log(max(p_{j,i}, eps)) / 2     half distance, eps = 2^-52
+ *                                                (eq. distmat), E[k][r][i] = 0
+ * bsnap, P, E: device, [T][R][N]; element type double for LS_FP64, float
+ * otherwise. bsnap[k] must be a backward table state at targets[k] for the
+ * same recipients (as written by ls_backward's snapshots); it may be NULL
+ * only if T == 0. Errors: LS_ERR_ARG, LS_ERR_STATE, LS_ERR_UNSUPPORTED,
+ * LS_ERR_DEVICE. */
+ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t *targets,
+                     int32_t T, const void *bsnap, void *P, void *E, void *stream);
+
+/* Backward (cf. Backward(bck, pars, t), section 3.6): moves `bck` from its
+ * current variant down to t (t < bck->l; an unpropagated table starts at
+ * variant L-1, where beta = 1, and may stop there, t <= L-1).
+ * targets: host, [T], strictly increasing, each in [t, bck->l) (or
+ * [t, L-1] for an unpropagated table), T <= 256. At each target k the
+ * backward vector beta^{targets[k]} is written to bsnap[k][r][j] (device,
+ * [T][R][N], double for LS_FP64 and float otherwise; diagonal 0).
+ * Errors: as ls_forward. */
+ls_status ls_backward(ls_table *bck, const ls_model *m, int32_t t, const int32_t *targets,
+                      int32_t T, void *bsnap, void *stream);
+
+/* Posterior and half distances from a forward and a backward table at the
+ * same variant for the same recipients (cf. PostProbs / DistMat, section 3.7):
+ *   P[r][j] = p_{j,i} (eq. postprob), E[r][j] = -log(max(p_{j,i}, eps))/2.
+ * P and E: device, [R][N], double for LS_FP64 tables and float otherwise;
+ * either may be NULL. Errors: LS_ERR_ARG, LS_ERR_STATE, LS_ERR_DEVICE. */
+ls_status ls_posterior_distance(const ls_table *fwd, const ls_table *bck, const ls_model *m,
+                                void *P, void *E, void *stream);
+
+/* Symmetrised local distances (eq. distmat) for T targets from half
+ * distances of all N recipients in order (recipient r = haplotype r):
+ *   D[k][a][b] = E[k][a][b] + E[k][b][a], D[k][a][a] = 0.
+ * E, D: device, [T][N][N], double if prec == LS_FP64 else float. D may
+ * equal E (in place). Errors: LS_ERR_ARG, LS_ERR_DEVICE. */
+ls_status ls_distance_symmetrise(const void *E, void *D, int32_t N, int32_t T,
+                                 ls_precision prec, void *stream);
+
+/* Log-likelihood of each recipient, log P(h_i | h_-i) = log F^{L-1}, their
+ * sum (the product-of-approximate-conditionals log-likelihood over all
+ * recipients, section 1) and, if grad_rho / grad_mu are not NULL, the
+ * gradient of that sum with respect to rho[0..L-2] and mu.
+ * recipients: device, [R] (NULL = all N haplotypes in order, R must be N).
+ * loglik: device [R] double (may be NULL); pac, grad_mu: device [1] double;
+ * grad_rho: device [L-1] double. The sum over recipients is taken in a fixed
+ * order, so results do not depend on scheduling.
+ * workspace: device, >= ls_loglik_grad_workspace_bytes(m, R, prec) bytes.
+ * Errors: LS_ERR_ARG, LS_ERR_WORKSPACE, LS_ERR_UNSUPPORTED, LS_ERR_DEVICE. */
+ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R,
+                         ls_precision prec, double *loglik, double *pac, double *grad_rho,
+                         double *grad_mu, void *workspace, size_t ws_bytes, void *stream);
+
+/* Workspace bytes ls_loglik_grad needs (0 on bad arguments). */
+size_t ls_loglik_grad_workspace_bytes(const ls_model *m, int32_t R, ls_precision prec);
+
+/* Synchronises `stream`, reads `R` status words and returns LS_OK,
+ * LS_WARN_NONFINITE if any recipient has LS_FLAG_NONFINITE, or LS_ERR_ARG if
+ * any has LS_FLAG_BAD_RECIPIENT. */
+ls_status ls_status_check(const uint32_t *status, int32_t R, void *stream);
+
+/* The kernel shape the library would use for N haplotypes at `prec`:
+ * slots (64-donor register groups) per wave and waves per recipient.
+ * Returns LS_ERR_UNSUPPORTED if no shape fits on one compute unit. */
+ls_status ls_kernel_shape(int32_t N, ls_precision prec, int32_t *slots_per_wave,
+                          int32_t *waves_per_recipient);
+
+const char *ls_status_string(ls_status s);
+const char *ls_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LS_H */

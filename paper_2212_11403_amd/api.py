@@ -1,0 +1,252 @@
+"""Python binding of libls over torch device tensors.
+
+Every function here only marshals arguments: it hands device pointers, sizes
+and the current HIP stream to the C ABI (include/ls.h); all arithmetic runs in
+the library's kernels. PyTorch provides device memory and streams.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (LS_FP32, LS_FP32_F16STORE, LS_FP64, LS_MAX_TARGETS, LsModel, LsTable,
+                   check)
+
+PRECISIONS = {"fp64": LS_FP64, "fp32": LS_FP32, "f16": LS_FP32_F16STORE}
+_STATE_DTYPE = {LS_FP64: torch.float64, LS_FP32: torch.float32, LS_FP32_F16STORE: torch.float16}
+_IO_DTYPE = {LS_FP64: torch.float64, LS_FP32: torch.float32, LS_FP32_F16STORE: torch.float32}
+
+
+def prec_code(prec) -> int:
+    if isinstance(prec, str):
+        return PRECISIONS[prec]
+    return int(prec)
+
+
+def io_dtype(prec) -> torch.dtype:
+    return _IO_DTYPE[prec_code(prec)]
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _p(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _i32_host(x) -> Optional[ctypes.Array]:
+    if x is None:
+        return None
+    arr = np.ascontiguousarray(np.asarray(x, dtype=np.int32))
+    return (ctypes.c_int32 * arr.size)(*arr.tolist())
+
+
+class Model:
+    """Haplotypes and parameters on the device (cf. kalis Parameters).
+
+    H: L x stride packed haplotypes (numpy uint32 or a device tensor).
+    rho: L-1 recombination probabilities; mu: mutation probability.
+    """
+
+    def __init__(self, H, N: int, rho, mu: float, device="cuda", stream=None):
+        lib = _lib.load()
+        dev = torch.device(device)
+        if isinstance(H, np.ndarray):
+            H = torch.from_numpy(np.ascontiguousarray(H, dtype=np.uint32).view(np.int32))
+        self.H = H.to(dev).contiguous()
+        if self.H.dtype not in (torch.int32, torch.uint32):
+            raise ValueError("H must hold 32-bit words")
+        L = int(self.H.shape[0])
+        rho = torch.as_tensor(np.asarray(rho, dtype=np.float64) if not torch.is_tensor(rho)
+                              else rho, dtype=torch.float64)
+        self.rho = rho.to(dev).contiguous()
+        if self.rho.numel() != max(L - 1, 0):
+            raise ValueError("rho must have L-1 entries")
+        self.c = LsModel()
+        self.c.H = self.H.data_ptr()
+        self.c.stride_words = int(self.H.shape[1])
+        self.c.N = int(N)
+        self.c.L = L
+        self.c.rho = self.rho.data_ptr() if self.rho.numel() else None
+        self.c.mu = float(mu)
+        nbytes = lib.ls_model_workspace_bytes(int(N), L)
+        if nbytes == 0:
+            raise ValueError("invalid N or L")
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+        check(lib.ls_model_init(ctypes.byref(self.c), _p(self.workspace), nbytes,
+                                _stream(stream)), "ls_model_init")
+        self.device = dev
+
+    @property
+    def N(self) -> int:
+        return self.c.N
+
+    @property
+    def L(self) -> int:
+        return self.c.L
+
+    @property
+    def mu(self) -> float:
+        return self.c.mu
+
+
+class Table:
+    """Forward (direction 0) or backward (direction 1) table for a set of
+    recipients (cf. MakeForwardTable / MakeBackwardTable)."""
+
+    def __init__(self, model: Model, direction: int, prec="fp32", recipients=None, stream=None):
+        lib = _lib.load()
+        self.prec = prec_code(prec)
+        dev = model.device
+        if recipients is None:
+            recipients = np.arange(model.N, dtype=np.int32)
+        self.recipients = torch.as_tensor(np.asarray(recipients, dtype=np.int32)).to(dev) \
+            if not torch.is_tensor(recipients) else recipients.to(dev, torch.int32).contiguous()
+        R = int(self.recipients.numel())
+        self.state = torch.zeros((R, model.N), dtype=_STATE_DTYPE[self.prec], device=dev)
+        self.log_scale = torch.zeros(R, dtype=torch.float64, device=dev)
+        self.status = torch.zeros(R, dtype=torch.int32, device=dev)
+        self.c = LsTable()
+        check(lib.ls_table_init(ctypes.byref(self.c), int(direction), self.prec, _p(self.state),
+                                _p(self.log_scale), _p(self.status), _p(self.recipients), R,
+                                _stream(stream)), "ls_table_init")
+        self.N = model.N
+
+    @property
+    def l(self) -> int:
+        return self.c.l
+
+    @property
+    def R(self) -> int:
+        return self.c.R
+
+    def copy_from(self, src: "Table", stream=None):
+        """CopyTable(self, src)."""
+        check(_lib.load().ls_table_copy(ctypes.byref(self.c), ctypes.byref(src.c), self.N,
+                                        _stream(stream)), "ls_table_copy")
+        self.recipients = src.recipients
+
+
+def forward(table: Table, model: Model, t: int, targets=None, bsnap=None, P=None, E=None,
+            stream=None):
+    T = 0 if targets is None else len(targets)
+    check(_lib.load().ls_forward(ctypes.byref(table.c), ctypes.byref(model.c), int(t),
+                                 _i32_host(targets), T, _p(bsnap), _p(P), _p(E),
+                                 _stream(stream)), "ls_forward")
+
+
+def backward(table: Table, model: Model, t: int, targets=None, bsnap=None, stream=None):
+    T = 0 if targets is None else len(targets)
+    check(_lib.load().ls_backward(ctypes.byref(table.c), ctypes.byref(model.c), int(t),
+                                  _i32_host(targets), T, _p(bsnap), _stream(stream)),
+          "ls_backward")
+
+
+def posterior_distance(fwd: Table, bck: Table, model: Model, P=None, E=None, stream=None):
+    check(_lib.load().ls_posterior_distance(ctypes.byref(fwd.c), ctypes.byref(bck.c),
+                                            ctypes.byref(model.c), _p(P), _p(E),
+                                            _stream(stream)), "ls_posterior_distance")
+
+
+def distance_symmetrise(E: torch.Tensor, D: Optional[torch.Tensor] = None, prec="fp32",
+                        stream=None) -> torch.Tensor:
+    """D[k] = E[k] + E[k]^T with a zero diagonal; E is [T][N][N] (or [N][N])."""
+    if D is None:
+        D = E
+    T = 1 if E.dim() == 2 else int(E.shape[0])
+    N = int(E.shape[-1])
+    check(_lib.load().ls_distance_symmetrise(_p(E), _p(D), N, T, prec_code(prec),
+                                             _stream(stream)), "ls_distance_symmetrise")
+    return D
+
+
+def status_check(table: Table, stream=None) -> int:
+    """LS_OK, or LS_WARN_NONFINITE if a recipient's column under/overflowed."""
+    code = _lib.load().ls_status_check(_p(table.status), table.R, _stream(stream))
+    if code not in (_lib.LS_OK, _lib.LS_WARN_NONFINITE):
+        check(code, "ls_status_check")
+    return code
+
+
+def kernel_shape(N: int, prec="fp32"):
+    a, b = ctypes.c_int32(0), ctypes.c_int32(0)
+    check(_lib.load().ls_kernel_shape(int(N), prec_code(prec), ctypes.byref(a), ctypes.byref(b)),
+          "ls_kernel_shape")
+    return a.value, b.value
+
+
+def loglik_grad(model: Model, recipients=None, prec="fp32", grad: bool = True, stream=None):
+    """Per-recipient log-likelihood, their sum (PAC) and optionally the
+    gradient of the sum w.r.t. rho (L-1) and mu. Returns a dict of device
+    tensors."""
+    lib = _lib.load()
+    pc = prec_code(prec)
+    dev = model.device
+    rec = None
+    if recipients is not None:
+        rec = torch.as_tensor(np.asarray(recipients, dtype=np.int32)).to(dev) \
+            if not torch.is_tensor(recipients) else recipients.to(dev, torch.int32).contiguous()
+    R = model.N if rec is None else int(rec.numel())
+    ll = torch.empty(R, dtype=torch.float64, device=dev)
+    pac = torch.empty(1, dtype=torch.float64, device=dev)
+    g_rho = torch.empty(max(model.L - 1, 1), dtype=torch.float64, device=dev) if grad else None
+    g_mu = torch.empty(1, dtype=torch.float64, device=dev) if grad else None
+    nbytes = lib.ls_loglik_grad_workspace_bytes(ctypes.byref(model.c), R, pc)
+    ws = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+    check(lib.ls_loglik_grad(ctypes.byref(model.c), _p(rec), R, pc, _p(ll), _p(pac), _p(g_rho),
+                             _p(g_mu), _p(ws), nbytes, _stream(stream)), "ls_loglik_grad")
+    out = dict(loglik=ll, pac=pac)
+    if grad:
+        out["grad_rho"] = g_rho[: max(model.L - 1, 0)]
+        out["grad_mu"] = g_mu
+    return out
+
+
+def decode(model: Model, targets: Sequence[int], prec="fp32", recipients=None,
+           want: Iterable[str] = ("E",), stream=None):
+    """Posterior decoding at several targets: a backward sweep that keeps
+    beta at the targets, then a forward sweep that combines alpha with it.
+
+    Returns a dict with any of P (posteriors) and E (half distances), each
+    [T][R][N], plus the two tables (whose log scales give the
+    log-likelihood at variant 0 / L-1)."""
+    targets = np.sort(np.asarray(targets, dtype=np.int32))
+    want = set(want)
+    pc = prec_code(prec)
+    fwd = Table(model, 0, pc, recipients, stream)
+    bck = Table(model, 1, pc, recipients, stream)
+    T, R, N = len(targets), fwd.R, model.N
+    dt = _IO_DTYPE[pc]
+    dev = model.device
+    P = torch.empty((T, R, N), dtype=dt, device=dev) if "P" in want else None
+    E = torch.empty((T, R, N), dtype=dt, device=dev) if "E" in want else None
+    bsnap = torch.empty((T, R, N), dtype=dt, device=dev)
+    # backward in chunks of at most LS_MAX_TARGETS targets, from the end
+    # (with T <= LS_MAX_TARGETS each direction is a single sweep launch)
+    hi = T
+    while hi > 0:
+        lo = max(0, hi - LS_MAX_TARGETS)
+        stop = 0 if lo == 0 else int(targets[lo])
+        backward(bck, model, stop, targets[lo:hi], bsnap[lo:hi], stream)
+        hi = lo
+    if bck.l != 0:
+        backward(bck, model, 0, None, None, stream)
+    for lo in range(0, T, LS_MAX_TARGETS):
+        hi = min(T, lo + LS_MAX_TARGETS)
+        stop = model.L - 1 if hi == T else int(targets[hi - 1])
+        forward(fwd, model, stop, targets[lo:hi], bsnap[lo:hi],
+                P[lo:hi] if P is not None else None, E[lo:hi] if E is not None else None, stream)
+    if fwd.l != model.L - 1:
+        forward(fwd, model, model.L - 1, None, None, None, None, stream)
+    return dict(P=P, E=E, fwd=fwd, bck=bck, bsnap=bsnap)

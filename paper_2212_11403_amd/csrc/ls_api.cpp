@@ -1,0 +1,473 @@
+// Host side of the C ABI declared in include/ls.h: argument validation,
+// kernel-shape selection, per-call scalar set-up and launches on the
+// caller's stream. No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "ls.h"
+#include "ls_internal.h"
+
+using lsk::Shape;
+using lsk::SweepArgs;
+using lsk::SweepPtrs;
+
+namespace {
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+ls_status dev(hipError_t e) { return e == hipSuccess ? LS_OK : LS_ERR_DEVICE; }
+
+bool valid_prec(int p) { return p == LS_FP64 || p == LS_FP32 || p == LS_FP32_F16STORE; }
+
+size_t state_elem(int prec) { return prec == LS_FP64 ? 8 : (prec == LS_FP32 ? 4 : 2); }
+size_t io_elem(int prec) { return prec == LS_FP64 ? 8 : 4; }
+
+int64_t hr_stride_for(int32_t N) {
+    const int64_t nf = N / 64;
+    const int64_t need = 2 * nf + 1;
+    return (need + 7) / 8 * 8;
+}
+
+uint64_t fnv1a(uint64_t h, const void *data, size_t n) {
+    const unsigned char *p = static_cast<const unsigned char *>(data);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// ---- kernel shapes ----------------------------------------------------------
+int vgpr_per_slot(int prec) { return prec == LS_FP64 ? 2 : 1; }
+
+bool in_menu(int prec, int n) {
+#define LS_MATCH(v) \
+    if (n == v) return true;
+    if (prec == LS_FP64) {
+        LS_MENU_F64(LS_MATCH)
+    } else {
+        LS_MENU_F32(LS_MATCH)
+    }
+#undef LS_MATCH
+    return false;
+}
+
+std::vector<int> menu(int prec, bool grad = false) {
+    std::vector<int> m;
+#define LS_PUSH(v) m.push_back(v);
+    if (grad) {
+        LS_MENU_GRAD(LS_PUSH)
+    } else if (prec == LS_FP64) {
+        LS_MENU_F64(LS_PUSH)
+    } else {
+        LS_MENU_F32(LS_PUSH)
+    }
+#undef LS_PUSH
+    return m;
+}
+
+// Does (nslot, nwaves) place every donor word of N haplotypes? Regular
+// slots must all hold full words and all words must be placed.
+bool shape_fits(int32_t N, int prec, int nslot, int nwaves) {
+    if (!in_menu(prec, nslot)) return false;
+    if (nwaves < 1 || nwaves > lsk::max_waves_for(nslot, vgpr_per_slot(prec))) return false;
+    const int NW = (N + 63) / 64, NF = N / 64;
+    const int K = lsk::special_slots(nslot);
+    return (int64_t)nwaves * (nslot - K) <= NF && (int64_t)nwaves * nslot >= NW;
+}
+
+// Cheapest shape: VALU issue slots per recipient step (four per 64-donor
+// slot plus the per-step reduction and scalar work, more with a workgroup
+// barrier), with a penalty when fewer than two waves share a SIMD (too little
+// to hide the per-step reduction latency).
+bool choose_shape(int32_t N, int prec, Shape *out, bool grad = false) {
+    if (const char *env = std::getenv("LS_FORCE_SHAPE")) {
+        int ns = 0, nw = 0;
+        if (std::sscanf(env, "%d,%d", &ns, &nw) == 2 && shape_fits(N, prec, ns, nw)) {
+            *out = Shape{ns, nw};
+            return true;
+        }
+    }
+    double best = 1e300;
+    bool found = false;
+    for (int nw = 1; nw <= lsk::kMaxWaves; ++nw) {
+        for (int ns : menu(prec, grad)) {
+            if (!shape_fits(N, prec, ns, nw)) continue;
+            const int need = ns * vgpr_per_slot(prec) + (prec == LS_FP64 ? 64 : 44);
+            const int wps = std::min(8, 512 / ((need + 7) / 8 * 8));
+            double cost = (double)nw * (4.0 * ns * (prec == LS_FP64 ? 1.25 : 1.0) + 40.0 +
+                                        (nw > 1 ? 30.0 : 0.0));
+            if (wps < 2) cost *= 1.5;
+            if (cost < best - 1e-9) {
+                best = cost;
+                *out = Shape{ns, nw};
+                found = true;
+            }
+        }
+    }
+    return found;
+}
+
+ls_status check_model(const ls_model *m) {
+    if (!m || !m->Hr || m->hash == 0 || m->N < 2 || m->L < 1) return LS_ERR_ARG;
+    return LS_OK;
+}
+
+void fill_scalars(SweepArgs &a, const ls_model *m, int prec, int dir) {
+    const double n1 = (double)(m->N - 1);
+    double kappa = 1.0;
+    if (prec == LS_FP32_F16STORE) kappa = dir == 0 ? 16384.0 : 16384.0 / n1;
+    a.hr_stride = m->hr_stride;
+    a.N = m->N;
+    a.L = m->L;
+    a.NF = m->N / 64;
+    a.mu = m->mu;
+    a.kappa = kappa;
+    a.inv_kappa = 1.0 / kappa;
+    if (dir == 0) {
+        a.cnum = kappa;
+        a.bmul = kappa / n1;
+        a.log_off = -std::log(kappa);
+    } else {
+        a.cnum = kappa * n1;
+        a.bmul = kappa;
+        a.log_off = -std::log(n1 * kappa);
+    }
+}
+
+hipError_t launch_sweep(int prec, int dir, const SweepPtrs &p, const SweepArgs &a, Shape sh,
+                        hipStream_t st) {
+    if (prec == LS_FP64)
+        return dir == 0 ? lsk::launch_sweep_f64_fwd(p, a, sh, st)
+                        : lsk::launch_sweep_f64_bwd(p, a, sh, st);
+    if (prec == LS_FP32)
+        return dir == 0 ? lsk::launch_sweep_f32_fwd(p, a, sh, st)
+                        : lsk::launch_sweep_f32_bwd(p, a, sh, st);
+    return dir == 0 ? lsk::launch_sweep_f16_fwd(p, a, sh, st)
+                    : lsk::launch_sweep_f16_bwd(p, a, sh, st);
+}
+
+ls_status check_table(const ls_table *t, const ls_model *m, int dir) {
+    if (!t || !t->state || !t->log_scale || !t->status || !t->recipients || t->R < 1)
+        return LS_ERR_ARG;
+    if (!valid_prec(t->prec)) return LS_ERR_ARG;
+    if (t->direction != dir) return LS_ERR_STATE;
+    if (t->model_hash != 0 && t->model_hash != m->hash) return LS_ERR_STATE;
+    if (t->l < -1 || t->l >= m->L) return LS_ERR_STATE;
+    return LS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ls_model_workspace_bytes(int32_t N, int32_t L) {
+    if (N < 2 || L < 1) return 0;
+    return (size_t)L * (size_t)hr_stride_for(N) * sizeof(uint64_t);
+}
+
+ls_status ls_model_init(ls_model *m, void *workspace, size_t ws_bytes, void *stream) {
+    if (!m || !m->H || m->N < 2 || m->L < 1) return LS_ERR_ARG;
+    if (m->stride_words < (m->N + 31) / 32 || (m->stride_words & 1)) return LS_ERR_ARG;
+    if (!(m->mu >= 0.0 && m->mu <= 1.0)) return LS_ERR_ARG;
+    if (m->L > 1 && !m->rho) return LS_ERR_ARG;
+    const size_t need = ls_model_workspace_bytes(m->N, m->L);
+    if (!workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
+        return LS_ERR_WORKSPACE;
+    hipStream_t st = as_stream(stream);
+    std::vector<double> rho((size_t)std::max(m->L - 1, 0));
+    if (!rho.empty()) {
+        hipError_t e = hipMemcpyAsync(rho.data(), m->rho, rho.size() * sizeof(double),
+                                      hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return LS_ERR_DEVICE;
+        for (double r : rho)
+            if (!(r >= 0.0 && r <= 1.0)) return LS_ERR_ARG;
+    }
+    uint64_t h = 1469598103934665603ull;
+    h = fnv1a(h, &m->N, sizeof m->N);
+    h = fnv1a(h, &m->L, sizeof m->L);
+    h = fnv1a(h, &m->mu, sizeof m->mu);
+    if (!rho.empty()) h = fnv1a(h, rho.data(), rho.size() * sizeof(double));
+    if (h == 0) h = 1;
+    const int64_t hs = hr_stride_for(m->N);
+    uint64_t *Hr = static_cast<uint64_t *>(workspace);
+    hipError_t e = lsk::launch_repack(m->H, m->stride_words, m->N, m->L, Hr, hs, st);
+    if (e != hipSuccess) return LS_ERR_DEVICE;
+    m->hash = h;
+    m->Hr = Hr;
+    m->hr_stride = hs;
+    m->nf = m->N / 64;
+    m->reserved = 0;
+    return LS_OK;
+}
+
+ls_status ls_table_init(ls_table *t, int32_t direction, ls_precision prec, void *state,
+                        double *log_scale, uint32_t *status, const int32_t *recipients,
+                        int32_t R, void *stream) {
+    if (!t || (direction != 0 && direction != 1) || !valid_prec(prec) || !state || !log_scale ||
+        !status || !recipients || R < 1)
+        return LS_ERR_ARG;
+    t->state = state;
+    t->log_scale = log_scale;
+    t->status = status;
+    t->recipients = recipients;
+    t->R = R;
+    t->l = -1;
+    t->direction = direction;
+    t->prec = prec;
+    t->model_hash = 0;
+    return dev(lsk::launch_fill_u32(status, 0u, R, as_stream(stream)));
+}
+
+ls_status ls_table_copy(ls_table *dst, const ls_table *src, int32_t N, void *stream) {
+    if (!dst || !src || N < 2 || !dst->state || !src->state || !dst->log_scale ||
+        !src->log_scale || !dst->status || !src->status)
+        return LS_ERR_ARG;
+    if (dst->direction != src->direction || dst->prec != src->prec || dst->R != src->R)
+        return LS_ERR_SHAPE;
+    hipStream_t st = as_stream(stream);
+    const size_t R = (size_t)src->R;
+    hipError_t e = hipMemcpyAsync(dst->state, src->state, R * (size_t)N * state_elem(src->prec),
+                                  hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dst->log_scale, src->log_scale, R * sizeof(double),
+                           hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dst->status, src->status, R * sizeof(uint32_t),
+                           hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return LS_ERR_DEVICE;
+    dst->recipients = src->recipients;
+    dst->l = src->l;
+    dst->model_hash = src->model_hash;
+    return LS_OK;
+}
+
+ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t *targets,
+                     int32_t T, const void *bsnap, void *P, void *E, void *stream) {
+    ls_status s = check_model(m);
+    if (s != LS_OK) return s;
+    if ((s = check_table(fwd, m, 0)) != LS_OK) return s;
+    if (t < 0 || t >= m->L || T < 0 || T > LS_MAX_TARGETS) return LS_ERR_ARG;
+    if (fwd->l >= 0 && t < fwd->l) return LS_ERR_STATE;
+    if (T > 0 && !targets) return LS_ERR_ARG;
+    const bool want_out = T > 0 && (P || E);
+    if (want_out && !bsnap) return LS_ERR_ARG;
+    for (int k = 0; k < T; ++k) {
+        if (targets[k] <= fwd->l || targets[k] > t) return LS_ERR_ARG;
+        if (k > 0 && targets[k] <= targets[k - 1]) return LS_ERR_ARG;
+    }
+    if (fwd->l == t) return T == 0 ? LS_OK : LS_ERR_ARG;
+    Shape sh;
+    if (!choose_shape(m->N, fwd->prec, &sh)) return LS_ERR_UNSUPPORTED;
+    SweepArgs a;
+    std::memset(&a, 0, sizeof a);
+    fill_scalars(a, m, fwd->prec, 0);
+    a.R = fwd->R;
+    a.dir = 0;
+    a.l0 = fwd->l;
+    a.t = t;
+    a.nt = want_out ? T : 0;
+    for (int k = 0; k < a.nt; ++k) {
+        a.tgt_l[k] = targets[k];
+        a.tgt_out[k] = k;
+    }
+    // forward vectors at the targets are staged in E (else P) and turned into
+    // posteriors / half distances in place afterwards
+    void *stage = E ? E : P;
+    SweepPtrs p;
+    p.Hr = m->Hr;
+    p.rho = m->L > 1 ? m->rho : reinterpret_cast<const double *>(m->Hr);  // only a discarded load when L == 1
+    p.recipients = fwd->recipients;
+    p.state = fwd->state;
+    p.log_scale = fwd->log_scale;
+    p.status = fwd->status;
+    p.snap = want_out ? stage : fwd->state;
+    hipStream_t st = as_stream(stream);
+    hipError_t e = launch_sweep(fwd->prec, 0, p, a, sh, st);
+    if (e != hipSuccess) return LS_ERR_DEVICE;
+    if (want_out) {
+        e = lsk::launch_posterior_rows(stage, 0, bsnap, 0, fwd->recipients, fwd->R,
+                                       (int64_t)T * fwd->R, m->N, fwd->prec == LS_FP64, P, E, st);
+        if (e != hipSuccess) return LS_ERR_DEVICE;
+    }
+    fwd->l = t;
+    fwd->model_hash = m->hash;
+    return LS_OK;
+}
+
+ls_status ls_backward(ls_table *bck, const ls_model *m, int32_t t, const int32_t *targets,
+                      int32_t T, void *bsnap, void *stream) {
+    ls_status s = check_model(m);
+    if (s != LS_OK) return s;
+    if ((s = check_table(bck, m, 1)) != LS_OK) return s;
+    if (t < 0 || t >= m->L || T < 0 || T > LS_MAX_TARGETS) return LS_ERR_ARG;
+    if (T > 0 && (!targets || !bsnap)) return LS_ERR_ARG;
+    const int32_t top = bck->l >= 0 ? bck->l : m->L - 1;
+    if (t > top) return LS_ERR_STATE;
+    for (int k = 0; k < T; ++k) {
+        if (targets[k] < t) return LS_ERR_ARG;
+        if (bck->l >= 0 ? targets[k] >= bck->l : targets[k] > m->L - 1) return LS_ERR_ARG;
+        if (k > 0 && targets[k] <= targets[k - 1]) return LS_ERR_ARG;
+    }
+    if (bck->l == t) return T == 0 ? LS_OK : LS_ERR_ARG;
+    Shape sh;
+    if (!choose_shape(m->N, bck->prec, &sh)) return LS_ERR_UNSUPPORTED;
+    SweepArgs a;
+    std::memset(&a, 0, sizeof a);
+    fill_scalars(a, m, bck->prec, 1);
+    a.R = bck->R;
+    a.dir = 1;
+    a.l0 = bck->l;
+    a.t = t;
+    a.nt = T;
+    for (int k = 0; k < T; ++k) {  // travel order: descending
+        a.tgt_l[k] = targets[T - 1 - k];
+        a.tgt_out[k] = T - 1 - k;
+    }
+    SweepPtrs p;
+    p.Hr = m->Hr;
+    p.rho = m->L > 1 ? m->rho : reinterpret_cast<const double *>(m->Hr);  // only a discarded load when L == 1
+    p.recipients = bck->recipients;
+    p.state = bck->state;
+    p.log_scale = bck->log_scale;
+    p.status = bck->status;
+    p.snap = T > 0 ? bsnap : bck->state;
+    hipError_t e = launch_sweep(bck->prec, 1, p, a, sh, as_stream(stream));
+    if (e != hipSuccess) return LS_ERR_DEVICE;
+    bck->l = t;
+    bck->model_hash = m->hash;
+    return LS_OK;
+}
+
+ls_status ls_posterior_distance(const ls_table *fwd, const ls_table *bck, const ls_model *m,
+                                void *P, void *E, void *stream) {
+    ls_status s = check_model(m);
+    if (s != LS_OK) return s;
+    if ((s = check_table(fwd, m, 0)) != LS_OK) return s;
+    if ((s = check_table(bck, m, 1)) != LS_OK) return s;
+    if (fwd->l < 0 || fwd->l != bck->l || fwd->R != bck->R || fwd->prec != bck->prec ||
+        fwd->recipients != bck->recipients || fwd->model_hash != m->hash ||
+        bck->model_hash != m->hash)
+        return LS_ERR_STATE;
+    if (!P && !E) return LS_OK;
+    const int half = fwd->prec == LS_FP32_F16STORE;
+    return dev(lsk::launch_posterior_rows(fwd->state, half, bck->state, half, fwd->recipients,
+                                          fwd->R, fwd->R, m->N, fwd->prec == LS_FP64, P, E,
+                                          as_stream(stream)));
+}
+
+ls_status ls_distance_symmetrise(const void *E, void *D, int32_t N, int32_t T,
+                                 ls_precision prec, void *stream) {
+    if (!E || !D || N < 1 || T < 0 || !valid_prec(prec)) return LS_ERR_ARG;
+    return dev(lsk::launch_symmetrise(E, D, N, T, prec == LS_FP64, as_stream(stream)));
+}
+
+size_t ls_loglik_grad_workspace_bytes(const ls_model *m, int32_t R, ls_precision prec) {
+    if (check_model(m) != LS_OK || R < 1 || !valid_prec(prec)) return 0;
+    return lsk::grad_workspace_bytes(m->N, m->L, R, (int)prec, nullptr);
+}
+
+ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R,
+                         ls_precision prec, double *loglik, double *pac, double *grad_rho,
+                         double *grad_mu, void *workspace, size_t ws_bytes, void *stream) {
+    ls_status s = check_model(m);
+    if (s != LS_OK) return s;
+    if (R < 1 || !valid_prec(prec) || !pac) return LS_ERR_ARG;
+    if (!recipients && R != m->N) return LS_ERR_ARG;
+    const bool grad = grad_rho || grad_mu;
+    if (grad && (!grad_mu || (m->L > 1 && !grad_rho))) return LS_ERR_ARG;
+    const size_t need = lsk::grad_workspace_bytes(m->N, m->L, R, (int)prec, nullptr);
+    if (!workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
+        return LS_ERR_WORKSPACE;
+    Shape sh;
+    if (!choose_shape(m->N, prec, &sh, grad)) return LS_ERR_UNSUPPORTED;
+    lsk::GradLayout lay;
+    lsk::grad_workspace_bytes(m->N, m->L, R, (int)prec, &lay);
+    char *ws = static_cast<char *>(workspace);
+    hipStream_t st = as_stream(stream);
+    const int32_t *rec = recipients;
+    if (!rec) {
+        int32_t *iota = reinterpret_cast<int32_t *>(ws + lay.off_recips);
+        hipError_t e = lsk::launch_iota(iota, R, st);
+        if (e != hipSuccess) return LS_ERR_DEVICE;
+        rec = iota;
+    }
+    // forward sweep of every recipient to the last variant: log F^{L-1}
+    ls_table tab;
+    s = ls_table_init(&tab, 0, prec, ws + lay.off_state, reinterpret_cast<double *>(ws + lay.off_ll),
+                      reinterpret_cast<uint32_t *>(ws + lay.off_status), rec, R, stream);
+    if (s != LS_OK) return s;
+    if (!grad) {
+        s = ls_forward(&tab, m, m->L - 1, nullptr, 0, nullptr, nullptr, nullptr, stream);
+        if (s != LS_OK) return s;
+        return dev(lsk::launch_loglik_sum(reinterpret_cast<const double *>(ws + lay.off_ll), R,
+                                          loglik, pac, st));
+    }
+    if (prec != LS_FP32 && prec != LS_FP64) return LS_ERR_UNSUPPORTED;
+    lsk::GradArgs ga;
+    std::memset(&ga, 0, sizeof ga);
+    ga.Hr = m->Hr;
+    ga.rho = m->L > 1 ? m->rho : reinterpret_cast<const double *>(m->Hr);
+    ga.recipients = rec;
+    ga.hr_stride = m->hr_stride;
+    ga.N = m->N;
+    ga.L = m->L;
+    ga.NF = m->N / 64;
+    ga.R = R;
+    ga.seg = lay.seg;
+    ga.nseg = lay.nseg;
+    ga.mu = m->mu;
+    ga.ws = ws;
+    ga.lay = lay;
+    return dev(lsk::launch_grad(ga, (int)prec, sh, loglik, pac, grad_rho, grad_mu, st));
+}
+
+ls_status ls_status_check(const uint32_t *status, int32_t R, void *stream) {
+    if (!status || R < 1) return LS_ERR_ARG;
+    std::vector<uint32_t> h((size_t)R);
+    hipStream_t st = as_stream(stream);
+    hipError_t e = hipMemcpyAsync(h.data(), status, h.size() * sizeof(uint32_t),
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return LS_ERR_DEVICE;
+    uint32_t any = 0;
+    for (uint32_t v : h) any |= v;
+    if (any & LS_FLAG_BAD_RECIPIENT) return LS_ERR_ARG;
+    if (any & LS_FLAG_NONFINITE) return LS_WARN_NONFINITE;
+    return LS_OK;
+}
+
+ls_status ls_kernel_shape(int32_t N, ls_precision prec, int32_t *slots_per_wave,
+                          int32_t *waves_per_recipient) {
+    if (N < 2 || !valid_prec(prec)) return LS_ERR_ARG;
+    Shape sh;
+    if (!choose_shape(N, prec, &sh)) return LS_ERR_UNSUPPORTED;
+    if (slots_per_wave) *slots_per_wave = sh.nslot;
+    if (waves_per_recipient) *waves_per_recipient = sh.nwaves;
+    return LS_OK;
+}
+
+const char *ls_status_string(ls_status s) {
+    switch (s) {
+    case LS_OK: return "ok";
+    case LS_ERR_ARG: return "invalid argument";
+    case LS_ERR_SHAPE: return "inconsistent sizes";
+    case LS_ERR_STATE: return "table in the wrong state for this call";
+    case LS_ERR_UNSUPPORTED: return "N too large for this precision on one GPU";
+    case LS_ERR_DEVICE: return "HIP runtime error";
+    case LS_ERR_WORKSPACE: return "workspace missing or too small";
+    case LS_WARN_NONFINITE: return "a column sum was zero or non-finite";
+    }
+    return "unknown status";
+}
+
+const char *ls_version(void) { return "libls 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,207 @@
+// Device helpers for gfx950: precision traits, wave64 DPP reductions and
+// workgroup reductions through LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ls_internal.h"
+
+namespace lsk {
+
+// ---------------------------------------------------------------------------
+// Precision traits. T: arithmetic type of the recursion. ST: type the resident
+// vector is kept in (registers and table). IO: type of snapshots, posteriors
+// and half distances.
+struct PrecF64 {
+    using T = double;
+    using ST = double;
+    using IO = double;
+    static constexpr int id = 0;
+    static constexpr int vgpr_per_slot = 2;
+};
+struct PrecF32 {
+    using T = float;
+    using ST = float;
+    using IO = float;
+    static constexpr int id = 1;
+    static constexpr int vgpr_per_slot = 1;
+};
+struct PrecF16 {
+    using T = float;
+    using ST = _Float16;
+    using IO = float;
+    static constexpr int id = 2;
+    static constexpr int vgpr_per_slot = 1;
+};
+
+// ---------------------------------------------------------------------------
+// Wave64 reductions with DPP. The pattern is fixed, so the summation order
+// is the same on every call: butterflies inside each quad, rotations inside
+// each 16-lane row, then the two row broadcasts, which leave the total in
+// lane 63; that lane is read into a scalar register.
+
+template <int CTRL, int ROWMASK = 0xF, int BANKMASK = 0xF, bool BOUND = true>
+__device__ __forceinline__ float dpp_f32(float x) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWMASK, BANKMASK, BOUND));
+}
+
+template <int CTRL, int ROWMASK = 0xF, int BANKMASK = 0xF, bool BOUND = true>
+__device__ __forceinline__ double dpp_f64(double x) {
+    int lo = __double2loint(x), hi = __double2hiint(x);
+    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWMASK, BANKMASK, BOUND);
+    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWMASK, BANKMASK, BOUND);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ float read_lane63(float x) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+__device__ __forceinline__ double read_lane63(double x) {
+    int lo = __builtin_amdgcn_readlane(__double2loint(x), 63);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(x), 63);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ float wave_sum(float x) {
+    x += dpp_f32<0xB1>(x);             // quad_perm [1,0,3,2]
+    x += dpp_f32<0x4E>(x);             // quad_perm [2,3,0,1]
+    x += dpp_f32<0x124>(x);            // row_ror:4
+    x += dpp_f32<0x128>(x);            // row_ror:8
+    x += dpp_f32<0x142, 0xA, 0xF, false>(x);  // row_bcast:15 into rows 1, 3
+    x += dpp_f32<0x143, 0xC, 0xF, false>(x);  // row_bcast:31 into rows 2, 3
+    return read_lane63(x);
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+    x += dpp_f64<0xB1>(x);
+    x += dpp_f64<0x4E>(x);
+    x += dpp_f64<0x124>(x);
+    x += dpp_f64<0x128>(x);
+    x += dpp_f64<0x142, 0xA, 0xF, false>(x);
+    x += dpp_f64<0x143, 0xC, 0xF, false>(x);
+    return read_lane63(x);
+}
+
+// Sum over the workgroup. Every wave returns the same value: each wave's
+// partial goes to its slot of a double-buffered LDS array and every wave adds
+// all MAXW slots in the same fixed tree (slots of absent waves stay 0), so
+// the result is identical across waves and runs. One barrier per call;
+// `parity` alternates so consecutive calls never reuse a buffer another wave
+// may still be reading. A single-wave group takes the same path (its other
+// slots are 0): a branch on the wave count, like a loop over it, makes the
+// register allocator spill the resident vector inside the variant loop.
+template <int MAXW, class T>
+__device__ __forceinline__ T block_sum(T x, T *red, int &parity, int wave, int nwaves) {
+    T w = wave_sum(x);
+    if constexpr (MAXW == 1) return w;
+    T *buf = red + parity * MAXW;
+    buf[wave] = w;
+    __syncthreads();
+    T p[MAXW];
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) p[k] = buf[k];
+#pragma unroll
+    for (int h = 1; h < MAXW; h *= 2)
+#pragma unroll
+        for (int k = 0; k + h < MAXW; k += 2 * h) p[k] += p[k + h];
+    parity ^= 1;
+    return p[0];
+}
+
+// Four sums at once with one barrier (same fixed trees as block_sum).
+// `red` holds 2 * 4 * MAXW entries.
+template <int MAXW, class T>
+__device__ __forceinline__ void block_sum4(T (&x)[4], T *red, int &parity, int wave) {
+    T w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[q] = wave_sum(x[q]);
+    if constexpr (MAXW == 1) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[q] = w[q];
+        return;
+    }
+    T *buf = red + parity * 4 * MAXW;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) buf[q * MAXW + wave] = w[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        T p[MAXW];
+#pragma unroll
+        for (int k = 0; k < MAXW; ++k) p[k] = buf[q * MAXW + k];
+#pragma unroll
+        for (int h = 1; h < MAXW; h *= 2)
+#pragma unroll
+            for (int k = 0; k + h < MAXW; k += 2 * h) p[k] += p[k + h];
+        x[q] = p[0];
+    }
+    parity ^= 1;
+}
+
+// Zero both buffers of a block_sum array (call once before the first use,
+// followed by a barrier).
+template <int MAXW, class T, int NV = 1>
+__device__ __forceinline__ void block_sum_init(T *red) {
+    for (int k = threadIdx.x; k < 2 * NV * MAXW; k += blockDim.x) red[k] = (T)0;
+}
+
+// ---------------------------------------------------------------------------
+// Raw buffer access. A buffer resource covers one row; the per-lane byte
+// offset stays in one VGPR and the per-slot offset is a scalar, so a long run
+// of loads or stores does not need one 64-bit VGPR address per access.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+template <class X>
+__device__ __forceinline__ X buf_load(rsrc_t rs, int voff, int soff);
+template <>
+__device__ __forceinline__ float buf_load<float>(rsrc_t rs, int voff, int soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(rsrc_t rs, int voff, int soff) {
+    auto u = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0);
+    return __hiloint2double((int)u[1], (int)u[0]);
+}
+template <>
+__device__ __forceinline__ _Float16 buf_load<_Float16>(rsrc_t rs, int voff, int soff) {
+    unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(rs, voff, soff, 0);
+    return __builtin_bit_cast(_Float16, u);
+}
+
+__device__ __forceinline__ void buf_store(float x, rsrc_t rs, int voff, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rs, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_store(double x, rsrc_t rs, int voff, int soff) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    u32x2 u;
+    u[0] = (unsigned int)__double2loint(x);
+    u[1] = (unsigned int)__double2hiint(x);
+    __builtin_amdgcn_raw_buffer_store_b64(u, rs, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_store(_Float16 x, rsrc_t rs, int voff, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), rs, voff, soff,
+                                          0);
+}
+
+__device__ __forceinline__ bool lane_bit(uint64_t mask) {
+    return __builtin_amdgcn_inverse_ballot_w64(mask);
+}
+
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// A copy of a scalar the compiler cannot see through. Address arithmetic of
+// rarely executed stores derives from it, so it is not hoisted out of the
+// variant loop (where it would pin one scalar register per slot).
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
+}  // namespace lsk

@@ -1,0 +1,150 @@
+// Internal definitions shared by the host C-ABI layer and the kernel
+// translation units. Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lsk {
+
+constexpr int kWave = 64;
+constexpr int kMaxWaves = 16;   // waves per recipient (1024-thread workgroup)
+constexpr int kMaxTargets = 256;
+constexpr uint32_t kFlagNonfinite = 1u;     // LS_FLAG_NONFINITE
+constexpr uint32_t kFlagBadRecipient = 2u;  // LS_FLAG_BAD_RECIPIENT
+
+// Arguments of one sweep launch (forward or backward) over R recipients.
+// The pointers travel as separate __restrict__ kernel parameters (so the
+// compiler may read the haplotype rows with scalar loads); everything else is
+// passed by value in this block.
+struct SweepPtrs {
+    const uint64_t *Hr;         // [L][hr_stride] internal rows (see ls_model_init)
+    const double *rho;          // [L-1]
+    const int32_t *recipients;  // [R]
+    void *state;                // table state [R][N]
+    double *log_scale;          // [R]
+    uint32_t *status;           // [R]
+    void *snap;                 // [T][R][N] vectors written at the targets
+};
+struct SweepArgs {
+    int64_t hr_stride;    // 64-bit words per internal row
+    int32_t N, L, NF, R;  // NF = floor(N/64) full words
+    int32_t dir;          // 0 forward, 1 backward
+    int32_t l0;           // current variant of the table (-1: not propagated)
+    int32_t t;            // variant to stop at
+    int32_t nt;           // number of targets visited, in travel order
+    double mu;
+    double kappa;         // storage scale of the resident vector
+    double inv_kappa;
+    double cnum;          // forward: kappa; backward: kappa * (N-1)
+    double bmul;          // forward: kappa / (N-1); backward: kappa
+    double log_off;       // per-step log offset: fwd -log(kappa), bwd -log((N-1) kappa)
+    int32_t tgt_l[kMaxTargets];    // variant of each visited target, travel order
+    int32_t tgt_out[kMaxTargets];  // its index k in the [T] output arrays
+};
+
+// Kernel shape: 64-donor register slots per wave, waves per recipient.
+struct Shape {
+    int nslot;
+    int nwaves;
+};
+
+// Largest workgroup (in waves) a kernel with `nslot` slots may be launched
+// with: the register file of one SIMD (512 VGPRs per lane) must hold every
+// wave the workgroup places on it. The constant covers the per-wave registers
+// besides the resident vector (emission pair, accumulators, special-slot
+// multipliers, the division and reduction temporaries).
+__host__ __device__ constexpr int max_waves_for(int nslot, int vgpr_per_slot) {
+    int need = nslot * vgpr_per_slot + (vgpr_per_slot == 2 ? 64 : 44);
+    need = (need + 7) / 8 * 8;
+    int per_simd = 512 / need;
+    if (per_simd > 8) per_simd = 8;
+    int w = 4 * per_simd;
+    return w > kMaxWaves ? kMaxWaves : (w < 1 ? 1 : w);
+}
+
+// Slot counts instantiated per precision. Every shape the host picks uses
+// one of these; the menu is dense enough that some number of waves fits
+// every N up to the register budget of one compute unit.
+#define LS_MENU_F32(X) \
+    X(1) X(2) X(3) X(4) X(8) X(12) X(16) X(20) X(24) X(28) X(32) X(40) X(48) X(56) X(64) \
+    X(72) X(80) X(88) X(96) X(104) X(112) X(120) X(128) X(136) X(144) X(152) X(160) X(164) \
+    X(168) X(172) X(176) X(180) X(184) X(188) X(192) X(196) X(200)
+#define LS_MENU_F64(X) \
+    X(1) X(2) X(3) X(4) X(8) X(12) X(16) X(20) X(24) X(28) X(32) X(40) X(48) X(56) X(64) \
+    X(68) X(72) X(76) X(80) X(84) X(88) X(92) X(96)
+
+// Slot counts of the gradient kernel (two precisions).
+#define LS_MENU_GRAD(X) \
+    X(1) X(2) X(3) X(4) X(8) X(12) X(16) X(20) X(24) X(28) X(32) X(40) X(48) X(56) X(64) \
+    X(72) X(80) X(88) X(96)
+
+// Launchers, one per precision and direction (ls_sweep_<prec>_<dir>.hip).
+// Return hipSuccess, hipErrorInvalidValue for a slot count that is not in
+// the menu, or the launch error.
+#define LS_DECLARE_LAUNCH(P, D)                                                          \
+    hipError_t launch_sweep_##P##_##D(const SweepPtrs &p, const SweepArgs &a, Shape shape, \
+                                      hipStream_t st);
+LS_DECLARE_LAUNCH(f64, fwd)
+LS_DECLARE_LAUNCH(f64, bwd)
+LS_DECLARE_LAUNCH(f32, fwd)
+LS_DECLARE_LAUNCH(f32, bwd)
+LS_DECLARE_LAUNCH(f16, fwd)
+LS_DECLARE_LAUNCH(f16, bwd)
+#undef LS_DECLARE_LAUNCH
+// Special (boundary) slots per wave for a given slot count.
+__host__ __device__ constexpr int special_slots(int nslot) { return nslot < 4 ? nslot : 4; }
+
+// Miscellaneous kernels (ls_misc.hip).
+hipError_t launch_repack(const uint32_t *H, int64_t stride_words, int32_t N, int32_t L,
+                         uint64_t *Hr, int64_t hr_stride, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
+hipError_t launch_symmetrise(const void *E, void *D, int32_t N, int32_t T, int is_f64,
+                             hipStream_t st);
+// Posterior and half distances for `rows` rows of length N: row q holds the
+// forward vector alpha[q] and backward vector beta[q] of recipient
+// recips[q % R]. P and E may be null; either may alias alpha (in place).
+// alpha/beta/P/E element types follow `prec` (half tables: ST = half).
+hipError_t launch_posterior_rows(const void *alpha, int alpha_half, const void *beta,
+                                 int beta_half, const int32_t *recips, int32_t R, int64_t rows,
+                                 int32_t N, int is_f64, void *P, void *E, hipStream_t st);
+
+// Log-likelihood and gradient (ls_grad.hip).
+// Workspace layout of ls_loglik_grad (byte offsets, 256-byte aligned).
+struct GradLayout {
+    size_t off_recips;  // int32 [R]   recipient indices when the caller passes none
+    size_t off_state;   // [R][N]      forward table of the log-likelihood pass
+    size_t off_ll;      // double [R]  per-recipient log-likelihood
+    size_t off_status;  // uint32 [R]
+    size_t off_ckpt;    // [R][nseg][N] forward vectors at checkpoints (gradient)
+    size_t off_seg;     // [R][seg][N]  forward vectors inside one segment
+    size_t off_grow;    // double [L-1][R] per-recipient d log P / d rho
+    size_t off_gmu;     // double [R]
+    size_t off_lsc;     // double [R] scratch log scale of the recompute sweeps
+    size_t off_ybuf;    // [R][N] backward vector handed between segments
+    size_t total;
+    int32_t seg, nseg;
+};
+// Fills *lay (if not null) and returns the workspace size.
+size_t grad_workspace_bytes(int32_t N, int32_t L, int32_t R, int prec, GradLayout *lay);
+
+struct GradArgs {
+    const uint64_t *Hr;
+    const double *rho;
+    const int32_t *recipients;
+    int64_t hr_stride;
+    int32_t N, L, NF, R;
+    int32_t seg, nseg;
+    double mu;
+    char *ws;
+    GradLayout lay;
+};
+hipError_t launch_iota(int32_t *p, int32_t n, hipStream_t st);
+// loglik[r] = ll[r] (if loglik != null) and *pac = sum_r ll[r] in index order
+hipError_t launch_loglik_sum(const double *ll, int32_t R, double *loglik, double *pac,
+                             hipStream_t st);
+hipError_t launch_grad(const GradArgs &a, int prec, Shape shape, double *loglik, double *pac,
+                       double *grad_rho, double *grad_mu, hipStream_t st);
+
+}  // namespace lsk

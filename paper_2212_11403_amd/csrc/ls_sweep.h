@@ -1,0 +1,355 @@
+// The sweep kernel: scaled forward (eq. fwd0/fwd1) and backward (eq.
+// bck0/bck1) recursions of the LS model for one recipient per workgroup,
+// with the posterior (eq. postprob) and half distances (eq. distmat) fused at
+// forward targets and beta snapshots written at backward targets.
+//
+// Both directions run the same update on a resident vector v:
+//   v <- theta^l (.) (c v + b),  c = num / sum(v_prev),  b = rho-term,
+// where (.) is the elementwise product and theta^l_j is 1-mu on a match of
+// donor j with the recipient at variant l and mu on a mismatch.
+//   forward:  v = kappa alpha^l,          c = (1-rho_{l-1}) kappa / S,
+//             b = kappa rho_{l-1} / (N-1); log F^l = log F^{l-1} + log(S_l / kappa)
+//   backward: v = kappa beta^l theta^l,   c = (1-rho_l) kappa (N-1) / S,
+//             b = kappa rho_l;            log G^l = log G^{l+1} + log(S_{l+1} / ((N-1) kappa))
+// (the backward form is eq. bck1 multiplied through by theta^l; c v + b is
+// kappa beta^l itself, which is what snapshots and tables store).
+//
+// Layout of one recipient's donor column. Donor j belongs to 64-bit word
+// j / 64 of a variant row, lane j % 64. Each wave holds NSLOT words ("slots")
+// in registers: slot s, lane x holds one donor. The words are handed out in a
+// rotated order that starts at the recipient's own word, so the self lane is
+// always in slot 0 of wave 0, and the last K slots of every wave ("special"
+// slots) take the remaining full words, the partial last word and empty
+// (phantom) slots. Slot 0 and the special slots add the rho-term through a
+// per-lane vector that is zero on the self lane and on lanes that hold no
+// donor, which keeps those entries exactly 0 with no per-cell cost. The
+// internal rows store every full word twice in a row, so the rotated words
+// of a wave are contiguous and are read with wide scalar loads; the mask of
+// one word drives v_cndmask for 64 donors at once.
+#pragma once
+
+#include <type_traits>
+
+#include "ls_device.h"
+
+namespace lsk {
+
+// Placement of one special slot.
+struct SpecSlot {
+    int off;         // offset of its word in the internal row
+    int word;        // donor word index (-1: phantom)
+    uint64_t valid;  // lanes that hold a donor (self included)
+    uint64_t bmask;  // lanes that hold a donor other than the recipient
+};
+
+__device__ __forceinline__ SpecSlot special_slot(int q, int NF, int N, int g, bool self_full,
+                                                 int sw, uint64_t self_bit) {
+    SpecSlot sp;
+    if (q < NF) {
+        int word = g + q;
+        sp.off = word;
+        if (word >= NF) word -= NF;
+        sp.word = word;
+        sp.valid = ~0ull;
+        sp.bmask = (self_full && word == sw) ? ~self_bit : ~0ull;
+    } else if ((N & 63) != 0 && q == NF) {
+        sp.off = 2 * NF;
+        sp.word = NF;
+        sp.valid = (1ull << (N & 63)) - 1ull;
+        sp.bmask = self_full ? sp.valid : (sp.valid & ~self_bit);
+    } else {
+        sp.off = 0;
+        sp.word = -1;
+        sp.valid = 0;
+        sp.bmask = 0;
+    }
+    return sp;
+}
+
+template <class PT, int NSLOT, int DIR>
+__global__ void __launch_bounds__(64 * max_waves_for(NSLOT, PT::vgpr_per_slot))
+sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
+             const int32_t *__restrict__ recipients, typename PT::ST *__restrict__ state,
+             double *__restrict__ log_scale, uint32_t *__restrict__ status,
+             typename PT::IO *__restrict__ snap, const SweepArgs a) {
+    // No contraction: the column sums add the rounded entries, exactly as
+    // the sum of a table loaded back from memory does, so a sweep resumed
+    // from a stored table gives the same bits as an uninterrupted one.
+#pragma clang fp contract(off)
+    using T = typename PT::T;
+    using ST = typename PT::ST;
+    using IO = typename PT::IO;
+    constexpr int K = special_slots(NSLOT);
+    constexpr int NR = NSLOT - K;
+    constexpr int MAXW = max_waves_for(NSLOT, PT::vgpr_per_slot);
+    __shared__ T red[2 * MAXW];
+
+    const int nwaves = uniform(blockDim.x >> 6);
+    const int wave = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int r = blockIdx.x;
+    const int N = a.N, NF = a.NF;
+    const int i = recipients[r];
+    if (i < 0 || i >= N) {
+        if (threadIdx.x == 0) status[r] |= kFlagBadRecipient;
+        return;
+    }
+    block_sum_init<MAXW>(red);
+    __syncthreads();
+    // ---- geometry --------------------------------------------------------
+    const int sw = i >> 6;
+    const uint64_t self_bit = 1ull << (i & 63);
+    const bool self_full = sw < NF;
+    const int g = self_full ? sw : 0;
+    const int reg_base = g + wave * NR;
+    const uint64_t m0 = (NR > 0 && wave == 0 && self_full) ? ~self_bit : ~0ull;
+    const int self_off = self_full ? sw : 2 * NF;
+    // per special slot: row offset of its word (scalar) and a 0/1 multiplier
+    // of the rho-term that is 0 on lanes without a donor or with the recipient
+    int spec_off[K];
+    T spec_keep[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        SpecSlot sp = special_slot(nwaves * NR + wave * K + k, NF, N, g, self_full, sw, self_bit);
+        spec_off[k] = sp.off;
+        spec_keep[k] = lane_bit(sp.bmask) ? (T)1 : (T)0;
+    }
+    const T keep0 = lane_bit(m0) ? (T)1 : (T)0;
+    // emissions in the form of appendix A.3, (1-H)(1-2mu)+mu, evaluated in
+    // FP64 and rounded once to the sweep precision
+    const T mu = (T)a.mu, omu = (T)((1.0 - 2.0 * a.mu) + a.mu);
+
+    ST v[NSLOT];
+    int parity = 0;
+    double prod = 1.0;  // running product of column sums: mantissa part
+    int expo = 0;       // and binary exponent
+    int nlog = 0;       // number of per-step log offsets to add
+    double base = 0.0;  // log scale the table started from
+    int kt = 0;         // next target, in travel order
+    T S;                // sum of the resident vector
+
+    // theta pair for variant l: value where the donor bit is 0, where it is 1
+    auto thetas = [&](const uint64_t *row, T &ta, T &tb) __attribute__((always_inline)) {
+        const bool rb = (row[self_off] & self_bit) != 0;
+        ta = rb ? mu : omu;
+        tb = rb ? omu : mu;
+    };
+    // Row words of slot s at variant row `row`.
+    auto mask_of = [&](const uint64_t *row, int s) __attribute__((always_inline)) -> uint64_t {
+        return (s < NR) ? row[reg_base + s] : row[spec_off[s - NR]];
+    };
+    // v <- theta^l (.) (c v + b); returns this lane's partial sum
+    auto step = [&](int l, T c, T b) __attribute__((always_inline)) -> T {
+        const uint64_t *row = Hr + (int64_t)l * a.hr_stride;
+        T ta, tb;
+        thetas(row, ta, tb);
+        T acc0 = 0, acc1 = 0;
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+            const T th = lane_bit(mask_of(row, s)) ? tb : ta;
+            const T bb = (s < NR) ? (s == 0 ? b * keep0 : b) : b * spec_keep[s - NR];
+            const T nv = th * fma(c, (T)v[s], bb);
+            v[s] = (ST)nv;
+            if (s & 1) acc1 += nv;
+            else acc0 += nv;
+        }
+        return acc0 + acc1;
+    };
+    // v <- c v + b (no emission): the backward vector before theta^l
+    auto affine = [&](T c, T b) __attribute__((always_inline)) {
+        const T b0 = b * keep0;
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+            const T bb = (s < NR) ? (s == 0 ? b0 : b) : b * spec_keep[s - NR];
+            v[s] = (ST)fma(c, (T)v[s], bb);
+        }
+    };
+    // v <- theta^l (.) v; returns this lane's partial sum
+    auto emit = [&](int l) __attribute__((always_inline)) -> T {
+        const uint64_t *row = Hr + (int64_t)l * a.hr_stride;
+        T ta, tb;
+        thetas(row, ta, tb);
+        T acc0 = 0, acc1 = 0;
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+            const T th = lane_bit(mask_of(row, s)) ? tb : ta;
+            const T nv = th * (T)v[s];
+            v[s] = (ST)nv;
+            if (s & 1) acc1 += nv;
+            else acc0 += nv;
+        }
+        return acc0 + acc1;
+    };
+    // write v (times `scale`, as type D) to a row of N elements starting at
+    // `dst`; the diagonal entry is written as 0 and lanes past N are skipped
+    auto store_row = [&](auto *dst, T scale) __attribute__((always_inline)) {
+        using D = typename std::remove_pointer<decltype(dst)>::type;
+        const rsrc_t rs = make_rsrc(dst, (uint32_t)N * sizeof(D));
+        const int voff = lane * (int)sizeof(D);
+        const int rb = opaque(reg_base);
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+            if (s < NR) {
+                int w = rb + s;
+                if (w >= NF) w -= NF;
+                T x = (T)v[s] * scale;
+                if (s == 0) x = lane_bit(m0) ? x : (T)0;
+                buf_store((D)x, rs, voff, w * 64 * (int)sizeof(D));
+            } else {
+                SpecSlot sp = special_slot(opaque(nwaves * NR + wave * K) + (s - NR), NF, N, g,
+                                           self_full, sw, self_bit);
+                if (lane_bit(sp.valid)) {
+                    T x = lane_bit(sp.bmask) ? (T)v[s] * scale : (T)0;
+                    buf_store((D)x, rs, voff, sp.word * 64 * (int)sizeof(D));
+                }
+            }
+        }
+    };
+    auto store_state = [&]() __attribute__((always_inline)) {
+        const rsrc_t rs = make_rsrc(state + (int64_t)r * N, (uint32_t)N * sizeof(ST));
+        const int voff = lane * (int)sizeof(ST);
+        const int rb = opaque(reg_base);
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+            if (s < NR) {
+                int w = rb + s;
+                if (w >= NF) w -= NF;
+                ST x = v[s];
+                if (s == 0) x = lane_bit(m0) ? x : (ST)0;
+                buf_store(x, rs, voff, w * 64 * (int)sizeof(ST));
+            } else {
+                SpecSlot sp = special_slot(opaque(nwaves * NR + wave * K) + (s - NR), NF, N, g,
+                                           self_full, sw, self_bit);
+                if (lane_bit(sp.valid))
+                    buf_store(lane_bit(sp.bmask) ? v[s] : (ST)0, rs, voff,
+                              sp.word * 64 * (int)sizeof(ST));
+            }
+        }
+    };
+    auto load_state = [&]() __attribute__((always_inline)) {
+        const rsrc_t rs = make_rsrc(state + (int64_t)r * N, (uint32_t)N * sizeof(ST));
+        const int voff = lane * (int)sizeof(ST);
+        const int rb = opaque(reg_base);
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+            if (s < NR) {
+                int w = rb + s;
+                if (w >= NF) w -= NF;
+                ST x = buf_load<ST>(rs, voff, w * 64 * (int)sizeof(ST));
+                if (s == 0) x = lane_bit(m0) ? x : (ST)0;
+                v[s] = x;
+            } else {
+                SpecSlot sp = special_slot(opaque(nwaves * NR + wave * K) + (s - NR), NF, N, g,
+                                           self_full, sw, self_bit);
+                ST x = (ST)0;
+                if (lane_bit(sp.bmask)) x = buf_load<ST>(rs, voff, sp.word * 64 * (int)sizeof(ST));
+                v[s] = x;
+            }
+        }
+    };
+    auto snapshot = [&]() __attribute__((always_inline)) {
+        IO *dst = snap + ((int64_t)a.tgt_out[kt] * a.R + r) * N;
+        store_row(dst, (T)a.inv_kappa);
+        ++kt;
+    };
+    // c = num / S, divided in the sweep precision
+    auto coef = [&](double num, T sum) __attribute__((always_inline)) -> T {
+        return (T)num / sum;
+    };
+    auto account = [&](T sum) __attribute__((always_inline)) {
+        int e;
+        prod = frexp(prod * (double)sum, &e);
+        expo += e;
+        ++nlog;
+    };
+
+    // ---- march ------------------------------------------------------------
+    // The variant loops below run only fused steps and contain no branches:
+    // with the whole donor column live in registers, any control flow inside
+    // them makes the register allocator spill. Targets, the first backward
+    // step and the last backward step are handled between loop segments.
+    const bool fresh = a.l0 < 0;
+    if (fresh) {
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) v[s] = (ST)0;
+    } else {
+        base = log_scale[r];
+        load_state();
+    }
+    if constexpr (DIR == 0) {
+        // alpha^0 = theta^0 pi (eq. fwd0), then eq. fwd1
+        int l;
+        S = (T)1;
+        if (fresh) {
+            l = 0;
+        } else {
+            l = a.l0 + 1;
+            T acc0 = 0, acc1 = 0;  // same order as in step()
+#pragma unroll
+            for (int s = 0; s < NSLOT; ++s) {
+                if (s & 1) acc1 += (T)v[s];
+                else acc0 += (T)v[s];
+            }
+            S = block_sum<MAXW>(acc0 + acc1, red, parity, wave, nwaves);
+        }
+        for (;;) {
+            const int lend = kt < a.nt ? a.tgt_l[kt] : a.t;
+            for (; l <= lend; ++l) {
+                // at l = 0: c = 0 and b = kappa/(N-1), which gives alpha^0
+                // (the load is unconditional: a branch here costs registers)
+                const double r0 = rho[l > 0 ? l - 1 : 0];
+                const double rr = l > 0 ? r0 : 1.0;
+                const double keep = l > 0 ? 1.0 : 0.0;
+                const T c = coef(keep * (1.0 - rr) * a.cnum, S);
+                const T b = (T)(rr * a.bmul);
+                T part = step(l, c, b);
+                S = block_sum<MAXW>(part, red, parity, wave, nwaves);
+                account(S);
+            }
+            if (kt < a.nt) snapshot();
+            if (lend >= a.t) break;
+        }
+    } else {
+        // beta^{L-1} = 1 (eq. bck0), then eq. bck1
+        const int lstart = fresh ? a.L - 1 : a.l0;
+        if (fresh) affine((T)0, (T)a.kappa);
+        if (kt < a.nt && a.tgt_l[kt] == lstart) snapshot();
+        if (a.t < lstart) {
+            T part = emit(lstart);
+            S = block_sum<MAXW>(part, red, parity, wave, nwaves);
+            int l = lstart - 1;
+            for (;;) {
+                const int lend = kt < a.nt ? a.tgt_l[kt] : a.t;
+                for (; l > lend; --l) {
+                    const double rr = rho[l];
+                    const T c = coef((1.0 - rr) * a.cnum, S);
+                    const T b = (T)(rr * a.bmul);
+                    account(S);
+                    part = step(l, c, b);
+                    S = block_sum<MAXW>(part, red, parity, wave, nwaves);
+                }
+                // l == lend: a target or the stopping variant; keep beta^l
+                const double rr = rho[l];
+                const T c = coef((1.0 - rr) * a.cnum, S);
+                const T b = (T)(rr * a.bmul);
+                account(S);
+                affine(c, b);
+                if (kt < a.nt && a.tgt_l[kt] == l) snapshot();
+                if (l <= a.t) break;
+                part = emit(l);
+                S = block_sum<MAXW>(part, red, parity, wave, nwaves);
+                --l;
+            }
+        }
+    }
+    store_state();
+    // ---- epilogue: log scale and status ------------------------------------
+    if (threadIdx.x == 0) {
+        const double ls = base + (log(prod) + (double)expo * 0.69314718055994530942) +
+                          (double)nlog * a.log_off;
+        log_scale[r] = ls;
+        if (!isfinite(ls)) status[r] |= kFlagNonfinite;
+    }
+}
+
+}  // namespace lsk

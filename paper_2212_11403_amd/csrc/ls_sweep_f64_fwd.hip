@@ -1,0 +1,28 @@
+// Sweep kernels for one precision and direction (see ls_sweep.h).
+#include "ls_sweep.h"
+
+namespace lsk {
+
+template <int NSLOT>
+static hipError_t launch_one(const SweepPtrs &p, const SweepArgs &a, int nwaves, hipStream_t st) {
+    using PT = PrecF64;
+    if (nwaves < 1 || nwaves > max_waves_for(NSLOT, PT::vgpr_per_slot)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sweep_kernel<PT, NSLOT, 0>), dim3(a.R), dim3(64 * nwaves), 0, st, p.Hr,
+                       p.rho, p.recipients, (PT::ST *)p.state, p.log_scale, p.status,
+                       (PT::IO *)p.snap, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_f64_fwd(const SweepPtrs &p, const SweepArgs &a, Shape shape, hipStream_t st) {
+    switch (shape.nslot) {
+#define LS_CASE(n) \
+    case n:        \
+        return launch_one<n>(p, a, shape.nwaves, st);
+        LS_MENU_F64(LS_CASE)
+#undef LS_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace lsk

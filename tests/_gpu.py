@@ -1,0 +1,56 @@
+"""Helpers for the GPU tests: device availability and tolerances."""
+
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+# FP64 path vs the FP64 oracle: relative 1e-12 per entry (plus a floor far
+# below any value the recursions produce). Quantities in the log domain
+# (half distances, log scales) carry the relative error of the probability
+# they come from as an absolute error, so they get an absolute 1e-12 floor.
+F64_RTOL = 1e-12
+F64_ATOL_PROB = 1e-300
+F64_ATOL_LOG = 1e-12
+# FP32 sweep: max abs posterior error.
+F32_POST_ATOL = 1e-5
+
+
+def need_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def rel_close(got, ref, rtol, atol):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    nan_g, nan_r = np.isnan(got), np.isnan(ref)
+    assert np.array_equal(nan_g, nan_r), "NaN pattern differs"
+    ok = ~nan_r
+    err = np.abs(got[ok] - ref[ok])
+    lim = rtol * np.abs(ref[ok]) + atol
+    bad = err > lim
+    if bad.any():
+        idx = np.argmax(err - lim)
+        raise AssertionError(f"{bad.sum()} entries out of tolerance; worst got={got[ok][idx]!r} "
+                             f"ref={ref[ok][idx]!r} err={err[idx]:.3e} lim={lim[idx]:.3e}")
+
+
+class forced_shape:
+    """Context manager: make the library use a given (slots, waves) shape."""
+
+    def __init__(self, nslot, nwaves):
+        self.v = f"{nslot},{nwaves}"
+
+    def __enter__(self):
+        self.old = os.environ.get("LS_FORCE_SHAPE")
+        os.environ["LS_FORCE_SHAPE"] = self.v
+
+    def __exit__(self, *a):
+        if self.old is None:
+            os.environ.pop("LS_FORCE_SHAPE", None)
+        else:
+            os.environ["LS_FORCE_SHAPE"] = self.old

@@ -1,0 +1,90 @@
+"""The C ABI library loads and exports every symbol include/ls.h declares.
+CPU only: no call here reaches the GPU (validation errors return before any
+HIP call, and the shape query is host arithmetic)."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ls.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ls_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2212_11403_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2212_11403_amd.build import build
+        build()
+    return _lib.load()
+
+
+def test_header_and_binding_agree(lib):
+    from paper_2212_11403_amd import _lib
+    assert _declared() == sorted(_lib.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2212_11403_amd import _lib
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    syms = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for name in _declared():
+        assert name in syms, name
+        assert getattr(lib, name) is not None
+
+
+def test_struct_layouts_match_header():
+    from paper_2212_11403_amd._lib import LsModel, LsTable
+    assert ctypes.sizeof(LsModel) == 72
+    assert ctypes.sizeof(LsTable) == 56
+
+
+def test_host_only_calls(lib):
+    assert lib.ls_version().decode().startswith("libls")
+    assert lib.ls_status_string(0).decode() == "ok"
+    assert lib.ls_status_string(16).decode().startswith("a column sum")
+    assert lib.ls_model_workspace_bytes(1, 10) == 0
+    # two copies of floor(N/64) words plus the partial word, padded to 64 B
+    assert lib.ls_model_workspace_bytes(200, 10) == 10 * 8 * 8
+    assert lib.ls_model_workspace_bytes(10000, 3) == 3 * 320 * 8
+
+
+def test_validation_errors_before_any_device_work(lib):
+    from paper_2212_11403_amd._lib import LsModel, LsTable
+    assert lib.ls_model_init(None, None, 0, None) == 1
+    m = LsModel()
+    m.N, m.L = 1, 5
+    assert lib.ls_model_init(ctypes.byref(m), None, 0, None) == 1
+    t = LsTable()
+    assert lib.ls_forward(None, ctypes.byref(m), 0, None, 0, None, None, None, None) == 1
+    assert lib.ls_forward(ctypes.byref(t), None, 0, None, 0, None, None, None, None) == 1
+    assert lib.ls_table_init(ctypes.byref(t), 2, 1, None, None, None, None, 0, None) == 1
+    assert lib.ls_distance_symmetrise(None, None, 3, 1, 1, None) == 1
+    assert lib.ls_status_check(None, 1, None) == 1
+
+
+def test_kernel_shapes_cover_every_size(lib):
+    """Every N up to the per-precision limit gets a shape that places all
+    donor words (host arithmetic only)."""
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    limits = {0: 45000, 1: 100000, 2: 100000}
+    for prec, nmax in limits.items():
+        for N in list(range(2, 3000)) + list(range(3000, nmax + 1, 997)) + [nmax]:
+            rc = lib.ls_kernel_shape(N, prec, ctypes.byref(a), ctypes.byref(b))
+            assert rc == 0, (prec, N)
+            ns, nw = a.value, b.value
+            K = min(ns, 4)
+            NW, NF = (N + 63) // 64, N // 64
+            assert nw * (ns - K) <= NF and nw * ns >= NW, (prec, N, ns, nw)

@@ -1,0 +1,150 @@
+"""Gradient of the PAC log-likelihood on the GPU vs the FP64 oracle's exact
+score and vs central finite differences of the FP64 GPU log-likelihood."""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from lsinputs import make_inputs, pack_haplotypes, rho_from_spacings, seeded_recipients
+
+from _gpu import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ls():
+    need_gpu()
+    import paper_2212_11403_amd as m
+    m.load()
+    return m
+
+
+def _case(N, L, seed, mu=0.01):
+    rng = np.random.default_rng(seed)
+    K = 6
+    F = (rng.random((L, K)) < 0.45).astype(np.uint8)
+    idx = rng.integers(0, K, size=N)
+    h = F[:, idx].copy()
+    sw = rng.random((L, N)) < 0.02
+    for j in range(N):
+        for l in np.nonzero(sw[:, j])[0]:
+            h[l:, j] = F[l:, rng.integers(0, K)]
+    h ^= (rng.random((L, N)) < 0.01).astype(np.uint8)
+    rho = rho_from_spacings(rng.exponential(0.02, L - 1))
+    return pack_haplotypes(h), rho, mu
+
+
+def _oracle_sum(H, N, L, rho, mu, rec):
+    g = oracle.run_gradient(H, N, L, rho, mu, rec)
+    return g["loglik"].sum(), g["grad_rho"].sum(axis=0), g["grad_mu"].sum()
+
+
+@pytest.mark.parametrize("N,L", [(2, 50), (40, 300), (130, 200)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gradient_vs_oracle(ls, N, L, prec):
+    H, rho, mu = _case(N, L, seed=N + L)
+    rec = np.arange(N, dtype=np.int32)
+    ll, gr, gm = _oracle_sum(H, N, L, rho, mu, rec)
+    m = ls.Model(H, N, rho, mu)
+    out = ls.loglik_grad(m, None, prec, grad=True)
+    pac = float(out["pac"].item())
+    g_rho = out["grad_rho"].cpu().numpy()
+    g_mu = float(out["grad_mu"].item())
+    ll_i = out["loglik"].cpu().numpy()
+    ref_i = oracle.run_pass(H, N, L, rho, mu, rec, want=())["llf"]
+    if prec == "fp64":
+        assert abs(pac - ll) <= 1e-12 * abs(ll)
+        assert np.allclose(ll_i, ref_i, rtol=1e-12, atol=1e-12)
+        scale = max(np.abs(gr).max(), 1.0)
+        assert np.abs(g_rho - gr).max() <= 1e-10 * scale
+        assert abs(g_mu - gm) <= 1e-10 * max(abs(gm), 1.0)
+    else:
+        assert abs(pac - ll) <= 1e-5 * abs(ll)
+        scale = np.abs(gr).max()
+        assert np.abs(g_rho - gr).max() <= 1e-4 * scale
+        assert abs(g_mu - gm) <= 1e-4 * max(abs(gm), 1.0)
+
+
+def test_gradient_recipient_subset(ls):
+    N, L = 100, 150
+    H, rho, mu = _case(N, L, seed=3)
+    rec = np.array([3, 50, 99, 0], np.int32)
+    ll, gr, gm = _oracle_sum(H, N, L, rho, mu, rec)
+    m = ls.Model(H, N, rho, mu)
+    out = ls.loglik_grad(m, rec, "fp64", grad=True)
+    assert abs(float(out["pac"].item()) - ll) <= 1e-12 * abs(ll)
+    assert np.abs(out["grad_rho"].cpu().numpy() - gr).max() <= 1e-10 * np.abs(gr).max()
+
+
+def test_gradient_matches_finite_differences(ls):
+    N, L = 60, 400
+    H, rho, mu = _case(N, L, seed=11)
+    m = ls.Model(H, N, rho, mu)
+    g = ls.loglik_grad(m, None, "fp64", grad=True)
+    g_rho = g["grad_rho"].cpu().numpy()
+
+    def pac(r, mm):
+        mod = ls.Model(H, N, r, mm)
+        return float(ls.loglik_grad(mod, None, "fp64", grad=False)["pac"].item())
+
+    rng = np.random.default_rng(0)
+    for l in rng.choice(np.nonzero(rho >= 1e-4)[0], 8, replace=False):
+        h = 1e-6 * rho[l]
+        rp, rm = rho.copy(), rho.copy()
+        rp[l] += h
+        rm[l] -= h
+        fd = (pac(rp, mu) - pac(rm, mu)) / (2 * h)
+        assert abs(fd - g_rho[l]) <= 1e-5 * max(abs(g_rho[l]), 1.0), (l, fd, g_rho[l])
+    h = 1e-6 * mu
+    fd = (pac(rho, mu + h) - pac(rho, mu - h)) / (2 * h)
+    assert abs(fd - float(g["grad_mu"].item())) <= 1e-5 * abs(fd)
+
+
+def test_autograd_function(ls):
+    import torch
+    N, L = 50, 120
+    H, rho, mu = _case(N, L, seed=12)
+    r = torch.tensor(rho, dtype=torch.float64, device="cuda", requires_grad=True)
+    m_ = torch.tensor(mu, dtype=torch.float64, device="cuda", requires_grad=True)
+    pac = ls.PACLoglik.apply(r, m_, H, N, "fp64")
+    pac.backward()
+    ll, gr, gm = _oracle_sum(H, N, L, rho, mu, np.arange(N, dtype=np.int32))
+    assert abs(pac.item() - ll) <= 1e-12 * abs(ll)
+    assert np.abs(r.grad.cpu().numpy() - gr).max() <= 1e-10 * np.abs(gr).max()
+    assert abs(m_.grad.item() - gm) <= 1e-10 * abs(gm)
+
+
+def test_differentiation_workload_sampled(ls):
+    """The differentiation workload (N = 2000, L = 50,000) at full size on a
+    seeded subset of recipients: FP32 adjoint vs the FP64 oracle's score and
+    vs central differences (h = 1e-6 relative) of the FP64 GPU PAC."""
+    x = make_inputs("c4")
+    N, L, rho, mu = x["N"], x["L"], x["rho"], x["mu"]
+    rec = seeded_recipients(N, 8, seed=404)
+    m = ls.Model(x["H"], N, rho, mu)
+    g32 = ls.loglik_grad(m, rec, "fp32", grad=True)
+    ll, gr, gm = _oracle_sum(x["H"], N, L, rho, mu, rec)
+    gr32 = g32["grad_rho"].cpu().numpy()
+    rel = np.abs(gr32 - gr).max() / np.abs(gr).max()
+    print(f"c4 fp32 adjoint vs oracle: norm-wise rel err {rel:.3e}; "
+          f"mu: {abs(g32['grad_mu'].item() - gm) / abs(gm):.3e}")
+    assert rel <= 1e-4
+    rng = np.random.default_rng(7)
+    cand = np.nonzero(rho >= 1e-4)[0]
+    picks = rng.choice(cand, 6, replace=False)
+
+    def pac(r):
+        mod = ls.Model(x["H"], N, r, mu)
+        return float(ls.loglik_grad(mod, rec, "fp64", grad=False)["pac"].item())
+
+    gmax = np.abs(gr32).max()
+    for l in picks:
+        h = 1e-6 * rho[l]
+        rp, rm = rho.copy(), rho.copy()
+        rp[l] += h
+        rm[l] -= h
+        fd = (pac(rp) - pac(rm)) / (2 * h)
+        assert abs(fd - gr32[l]) <= 1e-4 * gmax, (l, fd, gr32[l])

@@ -1,0 +1,289 @@
+"""GPU path vs the FP64 oracle, through the C ABI (libls.so)."""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from lsinputs import make_inputs, pack_haplotypes, rho_from_spacings
+
+from _gpu import (F32_POST_ATOL, F64_ATOL_LOG, F64_ATOL_PROB, F64_RTOL, forced_shape, need_gpu,
+                  rel_close)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ls():
+    need_gpu()
+    import paper_2212_11403_amd as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return make_inputs("c1")
+
+
+@pytest.fixture(scope="module")
+def c1_ref(c1):
+    x = c1
+    return oracle.run_pass(x["H"], x["N"], x["L"], x["rho"], x["mu"], np.arange(x["N"]),
+                           x["targets"], want=("A", "B", "P", "E", "logF", "logG"))
+
+
+def _np(t):
+    return t.double().cpu().numpy()
+
+
+def _random_case(N, L, seed, mu=0.01, d_mean=0.05):
+    rng = np.random.default_rng(seed)
+    # a few founders so that posteriors are not flat
+    K = max(2, min(8, N // 3))
+    F = (rng.random((L, K)) < 0.4).astype(np.uint8)
+    which = rng.integers(0, K, size=(L, N))
+    sw = rng.random((L, N)) < 0.05
+    base = rng.integers(0, K, size=N)
+    idx = np.where(np.cumsum(sw, axis=0) == 0, base[None, :], which)
+    h = F[np.arange(L)[:, None], idx]
+    flip = rng.random((L, N)) < 0.01
+    h = (h ^ flip).astype(np.uint8)
+    rho = rho_from_spacings(rng.exponential(d_mean, L - 1))
+    return pack_haplotypes(h), rho, mu
+
+
+# ---------------------------------------------------------------------------
+# the small plain-FP64 workload in full
+
+def test_c1_fp64_full_parity(ls, c1, c1_ref):
+    x, ref = c1, c1_ref
+    m = ls.Model(x["H"], x["N"], x["rho"], x["mu"])
+    r = ls.decode(m, x["targets"], "fp64", want=("P", "E"))
+    assert ls.status_check(r["fwd"]) == ls.LS_OK
+    rel_close(_np(r["P"]), ref["P"], F64_RTOL, F64_ATOL_PROB)
+    rel_close(_np(r["E"]), ref["E"], F64_RTOL, F64_ATOL_LOG)
+    rel_close(_np(r["bsnap"]), ref["B"], F64_RTOL, F64_ATOL_PROB)
+    rel_close(_np(r["fwd"].log_scale), ref["llf"], F64_RTOL, F64_ATOL_LOG)
+    # the backward table ends at variant 0: beta^0 and log G^0
+    ref0 = oracle.run_pass(x["H"], x["N"], x["L"], x["rho"], x["mu"], np.arange(x["N"]),
+                           np.array([0], np.int32), want=("B", "logG"))
+    rel_close(_np(r["bck"].state), ref0["B"][0], F64_RTOL, F64_ATOL_PROB)
+    rel_close(_np(r["bck"].log_scale), ref0["logG"][0], F64_RTOL, F64_ATOL_LOG)
+
+
+def test_c1_fp64_tables_at_every_target(ls, c1, c1_ref):
+    """alpha^t, beta^t and the log scales of tables stopped at each target."""
+    x, ref = c1, c1_ref
+    m = ls.Model(x["H"], x["N"], x["rho"], x["mu"])
+    fwd = ls.Table(m, 0, "fp64")
+    bck = ls.Table(m, 1, "fp64")
+    for k, t in enumerate(x["targets"]):
+        ls.forward(fwd, m, int(t))
+        rel_close(_np(fwd.state), ref["A"][k], F64_RTOL, F64_ATOL_PROB)
+        rel_close(_np(fwd.log_scale), ref["logF"][k], F64_RTOL, F64_ATOL_LOG)
+    for k in range(len(x["targets"]) - 1, -1, -1):
+        ls.backward(bck, m, int(x["targets"][k]))
+        rel_close(_np(bck.state), ref["B"][k], F64_RTOL, F64_ATOL_PROB)
+        rel_close(_np(bck.log_scale), ref["logG"][k], F64_RTOL, F64_ATOL_LOG)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "f16"])
+def test_c1_reduced_precision(ls, c1, c1_ref, prec):
+    x, ref = c1, c1_ref
+    m = ls.Model(x["H"], x["N"], x["rho"], x["mu"])
+    r = ls.decode(m, x["targets"], prec, want=("P", "E"))
+    err = np.abs(_np(r["P"]) - ref["P"]).max()
+    llerr = np.abs(_np(r["fwd"].log_scale) - ref["llf"]).max()
+    print(f"{prec}: max abs posterior error {err:.3e}, max abs loglik error {llerr:.3e}")
+    if prec == "fp32":
+        assert err <= F32_POST_ATOL
+        assert llerr <= 1e-3
+    else:
+        assert err <= 5e-2
+
+
+# ---------------------------------------------------------------------------
+# edge shapes: tiny N, word boundaries, partial words, several waves
+
+EDGE = [(2, 30), (3, 25), (63, 20), (64, 20), (65, 20), (127, 15), (128, 15), (129, 15),
+        (200, 12), (700, 8), (1031, 6)]
+
+
+@pytest.mark.parametrize("N,L", EDGE)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_edge_sizes(ls, N, L, prec):
+    H, rho, mu = _random_case(N, L, seed=N * 7 + L)
+    targets = np.unique(np.array([0, L // 3, L - 1], np.int32))
+    rec = np.arange(N, dtype=np.int32)
+    ref = oracle.run_pass(H, N, L, rho, mu, rec, targets, want=("P", "E", "A", "B"))
+    m = ls.Model(H, N, rho, mu)
+    r = ls.decode(m, targets, prec, want=("P", "E"))
+    if prec == "fp64":
+        rel_close(_np(r["P"]), ref["P"], F64_RTOL, F64_ATOL_PROB)
+        rel_close(_np(r["E"]), ref["E"], F64_RTOL, F64_ATOL_LOG)
+        rel_close(_np(r["fwd"].log_scale), ref["llf"], F64_RTOL, F64_ATOL_LOG)
+    else:
+        assert np.abs(_np(r["P"]) - ref["P"]).max() <= F32_POST_ATOL
+
+
+SHAPES = [  # (N, slots, waves): every wave layout class
+    (700, 4, 3), (700, 8, 2), (700, 3, 4), (700, 1, 11), (1031, 12, 2), (1031, 4, 5),
+    (1031, 2, 9), (333, 1, 6), (333, 2, 3), (4160, 12, 6), (4160, 16, 5),
+]
+
+
+@pytest.mark.parametrize("N,ns,nw", SHAPES)
+def test_forced_shapes_fp64(ls, N, ns, nw):
+    L = 9
+    H, rho, mu = _random_case(N, L, seed=N + 31 * ns + nw)
+    targets = np.array([2, 5], np.int32)
+    rec = np.array(sorted({0, 1, 63, 64, N // 2, N - 2, N - 1}), dtype=np.int32)
+    ref = oracle.run_pass(H, N, L, rho, mu, rec, targets, want=("P", "B", "A"))
+    m = ls.Model(H, N, rho, mu)
+    with forced_shape(ns, nw):
+        assert ls.kernel_shape(N, "fp64") == (ns, nw)
+        r = ls.decode(m, targets, "fp64", recipients=rec, want=("P",))
+    rel_close(_np(r["P"]), ref["P"], F64_RTOL, F64_ATOL_PROB)
+    rel_close(_np(r["bsnap"]), ref["B"], F64_RTOL, F64_ATOL_PROB)
+    rel_close(_np(r["fwd"].log_scale), ref["llf"], F64_RTOL, F64_ATOL_LOG)
+
+
+def test_recipient_subset_equals_full(ls, c1):
+    """Windows of recipients give the same columns (tables are independent
+    HMMs, section 3.9)."""
+    x = c1
+    m = ls.Model(x["H"], x["N"], x["rho"], x["mu"])
+    full = ls.decode(m, x["targets"], "fp64", want=("P",))
+    sub = np.array([5, 199, 0, 77], np.int32)
+    part = ls.decode(m, x["targets"], "fp64", recipients=sub, want=("P",))
+    assert np.array_equal(_np(part["P"]), _np(full["P"])[:, sub, :])
+
+
+def test_forward_in_steps_equals_direct(ls):
+    N, L = 150, 40
+    H, rho, mu = _random_case(N, L, seed=5)
+    m = ls.Model(H, N, rho, mu)
+    a = ls.Table(m, 0, "fp64")
+    ls.forward(a, m, 30)
+    b = ls.Table(m, 0, "fp64")
+    for t in range(0, 31):
+        ls.forward(b, m, t)
+    assert np.array_equal(_np(a.state), _np(b.state))
+    assert np.allclose(_np(a.log_scale), _np(b.log_scale), rtol=1e-13, atol=1e-12)
+    c = ls.Table(m, 1, "fp64")
+    ls.backward(c, m, 3)
+    d = ls.Table(m, 1, "fp64")
+    for t in range(L - 1, 2, -1):
+        ls.backward(d, m, t)
+    assert np.array_equal(_np(c.state), _np(d.state))
+    assert np.allclose(_np(c.log_scale), _np(d.log_scale), rtol=1e-13, atol=1e-12)
+
+
+def test_table_copy_then_propagate(ls):
+    N, L = 90, 20
+    H, rho, mu = _random_case(N, L, seed=6)
+    m = ls.Model(H, N, rho, mu)
+    a = ls.Table(m, 0, "fp32")
+    ls.forward(a, m, 7)
+    b = ls.Table(m, 0, "fp32")
+    b.copy_from(a)
+    ls.forward(b, m, 12)
+    ls.forward(a, m, 12)
+    assert np.array_equal(_np(a.state), _np(b.state))
+
+
+def test_posterior_distance_from_tables(ls, c1, c1_ref):
+    x, ref = c1, c1_ref
+    m = ls.Model(x["H"], x["N"], x["rho"], x["mu"])
+    import torch
+    for prec in ("fp64", "fp32", "f16"):
+        fwd = ls.Table(m, 0, prec)
+        bck = ls.Table(m, 1, prec)
+        t = int(x["targets"][3])
+        ls.forward(fwd, m, t)
+        ls.backward(bck, m, t)
+        dt = ls.io_dtype(prec)
+        P = torch.empty((x["N"], x["N"]), dtype=dt, device="cuda")
+        E = torch.empty_like(P)
+        ls.posterior_distance(fwd, bck, m, P, E)
+        if prec == "fp64":
+            rel_close(_np(P), ref["P"][3], F64_RTOL, F64_ATOL_PROB)
+            rel_close(_np(E), ref["E"][3], F64_RTOL, F64_ATOL_LOG)
+        elif prec == "fp32":
+            assert np.abs(_np(P) - ref["P"][3]).max() <= F32_POST_ATOL
+
+
+def test_distance_matrix(ls, c1, c1_ref):
+    x, ref = c1, c1_ref
+    m = ls.Model(x["H"], x["N"], x["rho"], x["mu"])
+    r = ls.decode(m, x["targets"], "fp64", want=("E",))
+    D = ls.distance_symmetrise(r["E"], prec="fp64")  # in place
+    Dref = np.stack([oracle.symmetrise(ref["E"][k]) for k in range(len(x["targets"]))])
+    rel_close(_np(D), Dref, F64_RTOL, F64_ATOL_LOG)
+    Dn = _np(D)
+    assert np.array_equal(Dn, np.transpose(Dn, (0, 2, 1)))
+
+
+def test_symmetrise_ragged_tiles(ls):
+    import torch
+    for N in (1, 5, 64, 65, 130):
+        E = torch.rand((3, N, N), dtype=torch.float32, device="cuda")
+        En = E.cpu().numpy().astype(np.float64)
+        D = torch.empty_like(E)
+        ls.distance_symmetrise(E, D, "fp32")
+        ref = En + np.transpose(En, (0, 2, 1))
+        for k in range(3):
+            np.fill_diagonal(ref[k], 0.0)
+        assert np.array_equal(D.cpu().numpy().astype(np.float64), ref.astype(np.float32).astype(np.float64))
+
+
+def test_total_underflow_nan_columns(ls):
+    """mu = 0 and a private allele of the recipient: its column becomes NaN
+    (diagonal 0) and the status word says so (appendix A.3)."""
+    L, N = 8, 6
+    rng = np.random.default_rng(21)
+    h = (rng.random((L, N)) < 0.5).astype(np.uint8)
+    h[3, :] = 0
+    h[3, 2] = 1
+    H = pack_haplotypes(h)
+    rho = np.full(L - 1, 0.1)
+    rec = np.array([2, 4], np.int32)
+    ref = oracle.run_pass(H, N, L, rho, 0.0, rec, np.array([5], np.int32), want=("P",))
+    m = ls.Model(H, N, rho, 0.0)
+    for prec in ("fp64", "fp32"):
+        r = ls.decode(m, [5], prec, recipients=rec, want=("P",))
+        P = _np(r["P"])[0]
+        assert np.array_equal(np.isnan(P), np.isnan(ref["P"][0]))
+        assert P[0, 2] == 0.0
+        assert ls.status_check(r["fwd"]) == ls.LS_WARN_NONFINITE
+
+
+def test_model_mismatch_is_rejected(ls):
+    N, L = 70, 10
+    H, rho, mu = _random_case(N, L, seed=8)
+    m1 = ls.Model(H, N, rho, mu)
+    m2 = ls.Model(H, N, rho * 0.5, mu)
+    t = ls.Table(m1, 0, "fp32")
+    ls.forward(t, m1, 3)
+    with pytest.raises(ls.LsError) as e:
+        ls.forward(t, m2, 5)
+    assert e.value.code == 3  # LS_ERR_STATE
+
+
+def test_argument_errors(ls):
+    N, L = 70, 10
+    H, rho, mu = _random_case(N, L, seed=9)
+    m = ls.Model(H, N, rho, mu)
+    t = ls.Table(m, 0, "fp32")
+    with pytest.raises(ls.LsError):
+        ls.forward(t, m, L)             # past the last variant
+    with pytest.raises(ls.LsError):
+        ls.forward(t, m, 5, targets=[4, 3], bsnap=t.state, E=t.state)  # not increasing
+    b = ls.Table(m, 1, "fp32")
+    with pytest.raises(ls.LsError):
+        ls.forward(b, m, 3)             # backward table given to forward
+    ls.forward(t, m, 6)
+    with pytest.raises(ls.LsError):
+        ls.forward(t, m, 4)             # cannot move backwards
