@@ -171,7 +171,9 @@ ls_status ls_backward(ls_table *bck, const ls_model *m, int32_t t, const int32_t
                       int32_t T, void *bsnap, void *stream);
 
 /* Posterior and half distances from a forward and a backward table at the
- * same variant for the same recipients (cf. PostProbs / DistMat, section 3.7):
+ * same variant (cf. PostProbs / DistMat, section 3.7). Both tables must hold
+ * the same recipients in the same order (not checked: they are device data);
+ * the recipient indices are read from fwd->recipients.
  *   P[r][j] = p_{j,i} (eq. postprob), E[r][j] = -log(max(p_{j,i}, eps))/2.
  * P and E: device, [R][N], double for LS_FP64 tables and float otherwise;
  * either may be NULL. Errors: LS_ERR_ARG, LS_ERR_STATE, LS_ERR_DEVICE. */

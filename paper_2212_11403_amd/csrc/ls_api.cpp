@@ -352,9 +352,10 @@ ls_status ls_posterior_distance(const ls_table *fwd, const ls_table *bck, const 
     if (s != LS_OK) return s;
     if ((s = check_table(fwd, m, 0)) != LS_OK) return s;
     if ((s = check_table(bck, m, 1)) != LS_OK) return s;
+    // (the recipient lists themselves are device memory; the caller
+    // guarantees both tables hold the same recipients in the same order)
     if (fwd->l < 0 || fwd->l != bck->l || fwd->R != bck->R || fwd->prec != bck->prec ||
-        fwd->recipients != bck->recipients || fwd->model_hash != m->hash ||
-        bck->model_hash != m->hash)
+        fwd->model_hash != m->hash || bck->model_hash != m->hash)
         return LS_ERR_STATE;
     if (!P && !E) return LS_OK;
     const int half = fwd->prec == LS_FP32_F16STORE;

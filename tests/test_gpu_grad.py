@@ -63,7 +63,8 @@ def test_gradient_vs_oracle(ls, N, L, prec):
         assert abs(g_mu - gm) <= 1e-10 * max(abs(gm), 1.0)
     else:
         assert abs(pac - ll) <= 1e-5 * abs(ll)
-        scale = np.abs(gr).max()
+        # norm-wise, with a floor: for N = 2 the exact rho gradient is 0
+        scale = max(np.abs(gr).max(), 1.0)
         assert np.abs(g_rho - gr).max() <= 1e-4 * scale
         assert abs(g_mu - gm) <= 1e-4 * max(abs(gm), 1.0)
 
