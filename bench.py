@@ -25,8 +25,59 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-VALU_PEAK = 256 * 4 * 16 * 2.4e9  # lane-operations/s: 256 CUs x 4 SIMD16 x 2.4 GHz
+# FP32 vector peak in lane-operations/s: 157.3 TFLOP/s counts an FMA as two
+# flops, i.e. 78.6e12 FP32 lane-operations/s = 256 CUs x 4 SIMDs x 32 lanes x
+# 2.4 GHz (each SIMD issues two wave64 FP32 instructions per four cycles,
+# which the SQ_ACTIVE_INST_VALU2 counter shows happening in this kernel).
+VALU_PEAK = 256 * 4 * 32 * 2.4e9
+# FP64 vector peak: 78.6 TFLOP/s, i.e. 39.3e12 FP64 FMA lane-operations/s.
+VALU_PEAK_F64 = 256 * 4 * 16 * 2.4e9
 OPS_PER_CELL = 4                  # emission select, FMA, MUL, ADD per cell per direction
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_bwd_fp32_c2_traffic.txt")
+SWEEP_SOURCES = ["ls_sweep.h", "ls_device.h", "ls_internal.h", "ls_sweep_f32_bwd.hip"]
+
+
+def sweep_source_hash():
+    """SHA-1 over the sources of the FP32 backward sweep kernel."""
+    import hashlib
+    h = hashlib.sha1()
+    for name in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2212_11403_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(shape):
+    """HBM bytes per launch of the backward sweep from the committed counter
+    summary, or None if it is absent or was taken on other kernel sources or
+    another kernel shape."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_sha1") != sweep_source_hash():
+            return None
+        if kv.get("shape") != f"{shape[0]}x{shape[1]}":
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """A plain 1 GiB device-to-device copy, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters (profiled under rocprofv3 --pmc)."""
+    import torch
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": 4 * n}), flush=True)
 
 
 def log(msg):
@@ -43,7 +94,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--err-recipients", type=int, default=256)
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1 "
                                    "(recipient sharding across GPUs is a design note only)"}))
@@ -153,14 +208,15 @@ def main():
     del p32
 
     # roofline of the dominant kernel (the backward sweep: one launch per step)
+    shape = ls.kernel_shape(N, "fp32")
     bwd_s = r32["bwd_ms"] / 1e3
     achieved = OPS_PER_CELL * cells / bwd_s
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                "unit": "TOP/s", "frac": achieved / VALU_PEAK, "traffic": None,
-                "kernel": "sweep_kernel (backward, FP32)",
+                "unit": "TOP/s", "frac": achieved / VALU_PEAK,
+                "traffic": measured_traffic(shape),
+                "kernel": f"sweep_kernel<PrecF32,{shape[0]},1> (backward)",
                 "ops_per_cell": OPS_PER_CELL, "cells_per_launch": cells,
                 "launch_ms": r32["bwd_ms"]}
-    shape = ls.kernel_shape(N, "fp32")
     line = {
         "metric": "LS fwd+bwd cell updates/s (N^2 L / s), FP32-scaled sweep",
         "value": value,
@@ -185,9 +241,12 @@ def main():
         "nonfinite_status": int(r32["status"]),
     }
     if r64 is not None:
+        a64 = OPS_PER_CELL * cells / (r64["bwd_ms"] / 1e3)
         line["fp64"] = {"value": cells / (r64["ms_per_step"] / 1e3), "ms_per_step":
                         r64["ms_per_step"], "backward_sweep_ms": r64["bwd_ms"],
-                        "forward_sweep_and_posterior_ms": r64["fwd_ms"]}
+                        "forward_sweep_and_posterior_ms": r64["fwd_ms"],
+                        "shape": list(ls.kernel_shape(N, "fp64")),
+                        "backward_alu_frac": a64 / VALU_PEAK_F64}
     line.update(err)
     print(json.dumps(line), flush=True)
 

@@ -82,10 +82,30 @@ bool shape_fits(int32_t N, int prec, int nslot, int nwaves) {
     return (int64_t)nwaves * (nslot - K) <= NF && (int64_t)nwaves * nslot >= NW;
 }
 
-// Cheapest shape: VALU issue slots per recipient step (four per 64-donor
-// slot plus the per-step reduction and scalar work, more with a workgroup
-// barrier), with a penalty when fewer than two waves share a SIMD (too little
-// to hide the per-step reduction latency).
+// Relative time of one recipient step for a shape, from a cost model fitted
+// to measured sweep times on MI355X (N = 2,000 .. 100,000, both precisions,
+// all recipients): the VALU work of the step (per slot and per wave) over all
+// waves of the group, inflated when a SIMD holds fewer waves than it needs to
+// hide the per-step load, reduction and barrier latency, and by the uneven
+// spread of the group's waves over the four SIMDs of a compute unit (every
+// step ends in a barrier, so the busiest SIMD sets the pace).
+double shape_cost(int32_t N, int prec, int ns, int nw) {
+    const bool f64 = prec == LS_FP64;
+    int need = ns * vgpr_per_slot(prec) + (f64 ? 64 : 44);
+    need = (need + 7) / 8 * 8;
+    const int wps = std::min(8, 512 / need);
+    // waves resident per SIMD when all N recipients are swept
+    const double occ = std::min<double>(wps, (double)N * nw / 1024.0);
+    const double ops = (f64 ? 5.83 : 4.0) * ns + 64.4;
+    const double hide = f64 ? 3.18 : 5.0;
+    const double imb = nw >= 4 ? ((nw + 3) / 4) / (nw / 4.0) : 1.0;
+    return (double)nw * ops * std::max(1.0, hide / occ) * std::pow(imb, 0.668);
+}
+
+// Cheapest shape by shape_cost; among shapes within 1% of the cheapest, the
+// one with the fewest waves (then the fewest slots). Depends on N and the
+// precision only, so a given problem always runs with the same summation
+// order.
 bool choose_shape(int32_t N, int prec, Shape *out, bool grad = false) {
     if (const char *env = std::getenv("LS_FORCE_SHAPE")) {
         int ns = 0, nw = 0;
@@ -95,23 +115,17 @@ bool choose_shape(int32_t N, int prec, Shape *out, bool grad = false) {
         }
     }
     double best = 1e300;
-    bool found = false;
-    for (int nw = 1; nw <= lsk::kMaxWaves; ++nw) {
-        for (int ns : menu(prec, grad)) {
-            if (!shape_fits(N, prec, ns, nw)) continue;
-            const int need = ns * vgpr_per_slot(prec) + (prec == LS_FP64 ? 64 : 44);
-            const int wps = std::min(8, 512 / ((need + 7) / 8 * 8));
-            double cost = (double)nw * (4.0 * ns * (prec == LS_FP64 ? 1.25 : 1.0) + 40.0 +
-                                        (nw > 1 ? 30.0 : 0.0));
-            if (wps < 2) cost *= 1.5;
-            if (cost < best - 1e-9) {
-                best = cost;
+    for (int nw = 1; nw <= lsk::kMaxWaves; ++nw)
+        for (int ns : menu(prec, grad))
+            if (shape_fits(N, prec, ns, nw)) best = std::min(best, shape_cost(N, prec, ns, nw));
+    if (best >= 1e300) return false;
+    for (int nw = 1; nw <= lsk::kMaxWaves; ++nw)
+        for (int ns : menu(prec, grad))
+            if (shape_fits(N, prec, ns, nw) && shape_cost(N, prec, ns, nw) <= best * 1.01) {
                 *out = Shape{ns, nw};
-                found = true;
+                return true;
             }
-        }
-    }
-    return found;
+    return false;
 }
 
 ls_status check_model(const ls_model *m) {

@@ -85,29 +85,51 @@ __device__ __forceinline__ double wave_sum(double x) {
 }
 
 // Sum over the workgroup. Every wave returns the same value: each wave's
-// partial goes to its slot of a double-buffered LDS array and every wave adds
-// all MAXW slots in the same fixed tree (slots of absent waves stay 0), so
-// the result is identical across waves and runs. One barrier per call;
-// `parity` alternates so consecutive calls never reuse a buffer another wave
-// may still be reading. A single-wave group takes the same path (its other
-// slots are 0): a branch on the wave count, like a loop over it, makes the
-// register allocator spill the resident vector inside the variant loop.
+// partial goes to its entry of a double-buffered LDS array of kRedStride
+// entries per buffer (entries of absent waves stay 0); lane k of every wave
+// then reads entry k and the first ceil-pow2(MAXW) lanes are added with the
+// same DPP butterflies on every wave, so the result is identical across waves
+// and runs. One barrier per call; `parity` alternates so consecutive calls
+// never reuse a buffer another wave may still be reading. A single-wave group
+// takes the same path (its other entries are 0): a branch on the wave count,
+// like a loop over it, makes the register allocator spill the resident vector
+// inside the variant loop.
+constexpr int kRedStride = 64;
+
+// Sum of lanes 0..MAXW-1 (MAXW <= 16), returned as a scalar. The quad
+// butterflies leave each quad's sum in all its lanes; row_ror:12 hands lane
+// k the value of lane k+4 (a rotation right by 12 within the 16-lane row),
+// which adds quad 1 to quad 0; row_ror:8 then adds lanes 8..15.
+template <int MAXW, class T>
+__device__ __forceinline__ T lanes_sum(T p) {
+    static_assert(MAXW <= 16, "cross-wave sums cover one 16-lane DPP row");
+    if constexpr (sizeof(T) == 4) {
+        if constexpr (MAXW > 1) p += dpp_f32<0xB1>(p);
+        if constexpr (MAXW > 2) p += dpp_f32<0x4E>(p);
+        if constexpr (MAXW > 4) p += dpp_f32<0x12C>(p);
+        if constexpr (MAXW > 8) p += dpp_f32<0x128>(p);
+        return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(p)));
+    } else {
+        if constexpr (MAXW > 1) p += dpp_f64<0xB1>(p);
+        if constexpr (MAXW > 2) p += dpp_f64<0x4E>(p);
+        if constexpr (MAXW > 4) p += dpp_f64<0x12C>(p);
+        if constexpr (MAXW > 8) p += dpp_f64<0x128>(p);
+        int lo = __builtin_amdgcn_readfirstlane(__double2loint(p));
+        int hi = __builtin_amdgcn_readfirstlane(__double2hiint(p));
+        return __hiloint2double(hi, lo);
+    }
+}
+
 template <int MAXW, class T>
 __device__ __forceinline__ T block_sum(T x, T *red, int &parity, int wave, int nwaves) {
     T w = wave_sum(x);
     if constexpr (MAXW == 1) return w;
-    T *buf = red + parity * MAXW;
+    T *buf = red + parity * kRedStride;
     buf[wave] = w;
     __syncthreads();
-    T p[MAXW];
-#pragma unroll
-    for (int k = 0; k < MAXW; ++k) p[k] = buf[k];
-#pragma unroll
-    for (int h = 1; h < MAXW; h *= 2)
-#pragma unroll
-        for (int k = 0; k + h < MAXW; k += 2 * h) p[k] += p[k + h];
+    T p = buf[threadIdx.x & 63];
     parity ^= 1;
-    return p[0];
+    return lanes_sum<MAXW>(p);
 }
 
 // Four sums at once with one barrier (same fixed trees as block_sum).
@@ -140,11 +162,13 @@ __device__ __forceinline__ void block_sum4(T (&x)[4], T *red, int &parity, int w
     parity ^= 1;
 }
 
-// Zero both buffers of a block_sum array (call once before the first use,
-// followed by a barrier).
+// Zero both buffers of a block_sum array (2 * kRedStride entries) or of a
+// block_sum4 array (2 * 4 * MAXW entries, NV = 4); call once before the first
+// use, followed by a barrier.
 template <int MAXW, class T, int NV = 1>
 __device__ __forceinline__ void block_sum_init(T *red) {
-    for (int k = threadIdx.x; k < 2 * NV * MAXW; k += blockDim.x) red[k] = (T)0;
+    constexpr int n = NV == 1 ? 2 * kRedStride : 2 * NV * MAXW;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) red[k] = (T)0;
 }
 
 // ---------------------------------------------------------------------------

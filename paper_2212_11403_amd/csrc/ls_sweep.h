@@ -82,7 +82,7 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
     constexpr int K = special_slots(NSLOT);
     constexpr int NR = NSLOT - K;
     constexpr int MAXW = max_waves_for(NSLOT, PT::vgpr_per_slot);
-    __shared__ T red[2 * MAXW];
+    __shared__ T red[2 * kRedStride];
 
     const int nwaves = uniform(blockDim.x >> 6);
     const int wave = uniform(threadIdx.x >> 6);
@@ -128,9 +128,14 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
     int kt = 0;         // next target, in travel order
     T S;                // sum of the resident vector
 
-    // theta pair for variant l: value where the donor bit is 0, where it is 1
-    auto thetas = [&](const uint64_t *row, T &ta, T &tb) __attribute__((always_inline)) {
-        const bool rb = (row[self_off] & self_bit) != 0;
+    // the recipient's own word of variant row l (read one step ahead)
+    auto self_word = [&](int l) __attribute__((always_inline)) -> uint64_t {
+        return Hr[(int64_t)l * a.hr_stride + self_off];
+    };
+    // theta pair for a variant whose recipient word is `sw_bits`: value where
+    // the donor bit is 0, where it is 1
+    auto thetas = [&](uint64_t sw_bits, T &ta, T &tb) __attribute__((always_inline)) {
+        const bool rb = (sw_bits & self_bit) != 0;
         ta = rb ? mu : omu;
         tb = rb ? omu : mu;
     };
@@ -139,10 +144,10 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
         return (s < NR) ? row[reg_base + s] : row[spec_off[s - NR]];
     };
     // v <- theta^l (.) (c v + b); returns this lane's partial sum
-    auto step = [&](int l, T c, T b) __attribute__((always_inline)) -> T {
+    auto step = [&](int l, uint64_t sw_bits, T c, T b) __attribute__((always_inline)) -> T {
         const uint64_t *row = Hr + (int64_t)l * a.hr_stride;
         T ta, tb;
-        thetas(row, ta, tb);
+        thetas(sw_bits, ta, tb);
         T acc0 = 0, acc1 = 0;
 #pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
@@ -168,7 +173,7 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
     auto emit = [&](int l) __attribute__((always_inline)) -> T {
         const uint64_t *row = Hr + (int64_t)l * a.hr_stride;
         T ta, tb;
-        thetas(row, ta, tb);
+        thetas(row[self_off], ta, tb);
         T acc0 = 0, acc1 = 0;
 #pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
@@ -252,9 +257,12 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
         store_row(dst, (T)a.inv_kappa);
         ++kt;
     };
-    // c = num / S, divided in the sweep precision
+    // c = num / S in the sweep precision: FP64 divides (correctly rounded),
+    // FP32 multiplies by the hardware reciprocal (within 1 ulp), which is
+    // below the rounding of the FP32 update itself
     auto coef = [&](double num, T sum) __attribute__((always_inline)) -> T {
-        return (T)num / sum;
+        if constexpr (sizeof(T) == 4) return (T)num * __builtin_amdgcn_rcpf(sum);
+        else return (T)num / sum;
     };
     auto account = [&](T sum) __attribute__((always_inline)) {
         int e;
@@ -292,17 +300,26 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
             }
             S = block_sum<MAXW>(acc0 + acc1, red, parity, wave, nwaves);
         }
+        // rho and the recipient's own word are read one variant ahead, so
+        // their latency overlaps the previous step
+        const int lmax = a.L - 1;
         for (;;) {
             const int lend = kt < a.nt ? a.tgt_l[kt] : a.t;
+            double r_nx = rho[l > 0 ? l - 1 : 0];
+            uint64_t w_nx = self_word(l <= lmax ? l : lmax);
             for (; l <= lend; ++l) {
                 // at l = 0: c = 0 and b = kappa/(N-1), which gives alpha^0
-                // (the load is unconditional: a branch here costs registers)
-                const double r0 = rho[l > 0 ? l - 1 : 0];
+                // (the loads are unconditional: a branch here costs registers)
+                const double r0 = r_nx;
+                const uint64_t wb = w_nx;
+                const int ln = l < lmax ? l + 1 : lmax;
+                r_nx = rho[ln > 0 ? ln - 1 : 0];
+                w_nx = self_word(ln);
                 const double rr = l > 0 ? r0 : 1.0;
                 const double keep = l > 0 ? 1.0 : 0.0;
                 const T c = coef(keep * (1.0 - rr) * a.cnum, S);
                 const T b = (T)(rr * a.bmul);
-                T part = step(l, c, b);
+                T part = step(l, wb, c, b);
                 S = block_sum<MAXW>(part, red, parity, wave, nwaves);
                 account(S);
             }
@@ -320,12 +337,19 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
             int l = lstart - 1;
             for (;;) {
                 const int lend = kt < a.nt ? a.tgt_l[kt] : a.t;
+                // rho and the recipient's own word are read one variant ahead
+                double r_nx = rho[l];
+                uint64_t w_nx = self_word(l);
                 for (; l > lend; --l) {
-                    const double rr = rho[l];
+                    const double rr = r_nx;
+                    const uint64_t wb = w_nx;
+                    const int ln = l > 0 ? l - 1 : 0;
+                    r_nx = rho[ln];
+                    w_nx = self_word(ln);
                     const T c = coef((1.0 - rr) * a.cnum, S);
                     const T b = (T)(rr * a.bmul);
                     account(S);
-                    part = step(l, c, b);
+                    part = step(l, wb, c, b);
                     S = block_sum<MAXW>(part, red, parity, wave, nwaves);
                 }
                 // l == lend: a target or the stopping variant; keep beta^l

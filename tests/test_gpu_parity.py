@@ -150,6 +150,34 @@ def test_forced_shapes_fp64(ls, N, ns, nw):
     rel_close(_np(r["fwd"].log_scale), ref["llf"], F64_RTOL, F64_ATOL_LOG)
 
 
+WIDE_SHAPES = [  # (precision, N, slots, waves): groups of 5..12 waves with wide slots, where
+    # the cross-wave sum covers 8 or 12 lanes (the register budget of the slot
+    # count caps the group at 8 or 12 waves)
+    ("fp64", 20000, 56, 6), ("fp64", 40000, 80, 8), ("fp64", 26000, 40, 11),
+    ("fp32", 54000, 172, 5), ("fp32", 100000, 196, 8), ("fp32", 58000, 104, 9),
+]
+
+
+@pytest.mark.parametrize("prec,N,ns,nw", WIDE_SHAPES)
+def test_forced_wide_shapes(ls, prec, N, ns, nw):
+    L = 9
+    H, rho, mu = _random_case(N, L, seed=N + ns + nw)
+    targets = np.array([2, 5], np.int32)
+    rec = np.array(sorted({0, 1, 63, 64, N // 2, N - 2, N - 1}), dtype=np.int32)
+    ref = oracle.run_pass(H, N, L, rho, mu, rec, targets, want=("P", "B"))
+    m = ls.Model(H, N, rho, mu)
+    with forced_shape(ns, nw):
+        assert ls.kernel_shape(N, prec) == (ns, nw)
+        r = ls.decode(m, targets, prec, recipients=rec, want=("P",))
+    if prec == "fp64":
+        rel_close(_np(r["P"]), ref["P"], F64_RTOL, F64_ATOL_PROB)
+        rel_close(_np(r["bsnap"]), ref["B"], F64_RTOL, F64_ATOL_PROB)
+        rel_close(_np(r["fwd"].log_scale), ref["llf"], F64_RTOL, F64_ATOL_LOG)
+    else:
+        assert np.abs(_np(r["P"]) - ref["P"]).max() <= F32_POST_ATOL
+        assert np.max(np.abs(_np(r["fwd"].log_scale) - ref["llf"]) / np.abs(ref["llf"])) <= 1e-5
+
+
 def test_recipient_subset_equals_full(ls, c1):
     """Windows of recipients give the same columns (tables are independent
     HMMs, section 3.9)."""
