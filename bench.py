@@ -71,13 +71,15 @@ def copy_calibration():
     """A plain 1 GiB device-to-device copy, for scaling the FETCH_SIZE and
     WRITE_SIZE counters (profiled under rocprofv3 --pmc)."""
     import torch
-    n = 1 << 28
+    n = 1 << 29  # 2 GiB per buffer, well above the 256 MB last-level cache
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_calibration_bytes": 4 * n}), flush=True)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)  # elementwise kernel: reads and writes 2 GiB
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n}),
+          flush=True)
 
 
 def log(msg):

@@ -61,9 +61,11 @@ typedef enum {
  * LS_FP32: single-precision vectors with per-step renormalisation; column
  *   sums reduced in FP32 lanes; the log scale factors and the
  *   log-likelihood accumulate in FP64.
- * LS_FP32_F16STORE: as LS_FP32 but the resident forward/backward vectors are
- *   stored in IEEE half precision, multiplied by a fixed per-direction scale
- *   kappa (see ls_table); arithmetic is FP32. A precision-study option. */
+ * LS_FP32_F16STORE: as LS_FP32 during a sweep (the vectors stay in FP32
+ *   registers); the tables between sweeps hold the vectors in IEEE half
+ *   precision, multiplied by a fixed per-direction scale kappa (see ls_table),
+ *   which halves their memory. Snapshots, posteriors and distances are FP32.
+ *   A precision-study option: each store to a table rounds to half. */
 typedef enum { LS_FP64 = 0, LS_FP32 = 1, LS_FP32_F16STORE = 2 } ls_precision;
 
 /* Status word flags (per recipient, device memory). */

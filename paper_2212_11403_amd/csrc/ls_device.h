@@ -199,19 +199,33 @@ __device__ __forceinline__ _Float16 buf_load<_Float16>(rsrc_t rs, int voff, int 
     return __builtin_bit_cast(_Float16, u);
 }
 
-__device__ __forceinline__ void buf_store(float x, rsrc_t rs, int voff, int soff) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rs, voff, soff, 0);
+// Stores take a cache policy: 0 (default) or kStreaming (the `nt` bit), for
+// data written once and read by a later kernel (snapshots), so the streamed
+// rows do not displace the haplotype rows the sweep keeps reading.
+constexpr int kStreaming = 2;
+
+__device__ __forceinline__ void buf_store(float x, rsrc_t rs, int voff, int soff, int pol = 0) {
+    if (pol == kStreaming)
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rs, voff, soff, kStreaming);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rs, voff, soff, 0);
 }
-__device__ __forceinline__ void buf_store(double x, rsrc_t rs, int voff, int soff) {
+__device__ __forceinline__ void buf_store(double x, rsrc_t rs, int voff, int soff, int pol = 0) {
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
     u32x2 u;
     u[0] = (unsigned int)__double2loint(x);
     u[1] = (unsigned int)__double2hiint(x);
-    __builtin_amdgcn_raw_buffer_store_b64(u, rs, voff, soff, 0);
+    if (pol == kStreaming)
+        __builtin_amdgcn_raw_buffer_store_b64(u, rs, voff, soff, kStreaming);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(u, rs, voff, soff, 0);
 }
-__device__ __forceinline__ void buf_store(_Float16 x, rsrc_t rs, int voff, int soff) {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), rs, voff, soff,
-                                          0);
+__device__ __forceinline__ void buf_store(_Float16 x, rsrc_t rs, int voff, int soff, int pol = 0) {
+    const unsigned short u = __builtin_bit_cast(unsigned short, x);
+    if (pol == kStreaming)
+        __builtin_amdgcn_raw_buffer_store_b16(u, rs, voff, soff, kStreaming);
+    else
+        __builtin_amdgcn_raw_buffer_store_b16(u, rs, voff, soff, 0);
 }
 
 __device__ __forceinline__ bool lane_bit(uint64_t mask) {

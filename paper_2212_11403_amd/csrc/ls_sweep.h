@@ -68,6 +68,7 @@ __device__ __forceinline__ SpecSlot special_slot(int q, int NF, int N, int g, bo
 
 template <class PT, int NSLOT, int DIR>
 __global__ void __launch_bounds__(64 * max_waves_for(NSLOT, PT::vgpr_per_slot))
+__attribute__((amdgpu_waves_per_eu(sweep_waves_per_simd(NSLOT, PT::vgpr_per_slot))))
 sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
              const int32_t *__restrict__ recipients, typename PT::ST *__restrict__ state,
              double *__restrict__ log_scale, uint32_t *__restrict__ status,
@@ -119,7 +120,9 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
     // FP64 and rounded once to the sweep precision
     const T mu = (T)a.mu, omu = (T)((1.0 - 2.0 * a.mu) + a.mu);
 
-    ST v[NSLOT];
+    // resident vector in the arithmetic precision; the table state (ST) is
+    // converted only when it is loaded or stored
+    T v[NSLOT];
     int parity = 0;
     double prod = 1.0;  // running product of column sums: mantissa part
     int expo = 0;       // and binary exponent
@@ -154,7 +157,7 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
             const T th = lane_bit(mask_of(row, s)) ? tb : ta;
             const T bb = (s < NR) ? (s == 0 ? b * keep0 : b) : b * spec_keep[s - NR];
             const T nv = th * fma(c, (T)v[s], bb);
-            v[s] = (ST)nv;
+            v[s] = nv;
             if (s & 1) acc1 += nv;
             else acc0 += nv;
         }
@@ -166,7 +169,7 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
 #pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
             const T bb = (s < NR) ? (s == 0 ? b0 : b) : b * spec_keep[s - NR];
-            v[s] = (ST)fma(c, (T)v[s], bb);
+            v[s] = fma(c, v[s], bb);
         }
     };
     // v <- theta^l (.) v; returns this lane's partial sum
@@ -178,8 +181,8 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
 #pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
             const T th = lane_bit(mask_of(row, s)) ? tb : ta;
-            const T nv = th * (T)v[s];
-            v[s] = (ST)nv;
+            const T nv = th * v[s];
+            v[s] = nv;
             if (s & 1) acc1 += nv;
             else acc0 += nv;
         }
@@ -199,13 +202,13 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
                 if (w >= NF) w -= NF;
                 T x = (T)v[s] * scale;
                 if (s == 0) x = lane_bit(m0) ? x : (T)0;
-                buf_store((D)x, rs, voff, w * 64 * (int)sizeof(D));
+                buf_store((D)x, rs, voff, w * 64 * (int)sizeof(D), kStreaming);
             } else {
                 SpecSlot sp = special_slot(opaque(nwaves * NR + wave * K) + (s - NR), NF, N, g,
                                            self_full, sw, self_bit);
                 if (lane_bit(sp.valid)) {
                     T x = lane_bit(sp.bmask) ? (T)v[s] * scale : (T)0;
-                    buf_store((D)x, rs, voff, sp.word * 64 * (int)sizeof(D));
+                    buf_store((D)x, rs, voff, sp.word * 64 * (int)sizeof(D), kStreaming);
                 }
             }
         }
@@ -219,14 +222,14 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
             if (s < NR) {
                 int w = rb + s;
                 if (w >= NF) w -= NF;
-                ST x = v[s];
+                ST x = (ST)v[s];
                 if (s == 0) x = lane_bit(m0) ? x : (ST)0;
                 buf_store(x, rs, voff, w * 64 * (int)sizeof(ST));
             } else {
                 SpecSlot sp = special_slot(opaque(nwaves * NR + wave * K) + (s - NR), NF, N, g,
                                            self_full, sw, self_bit);
                 if (lane_bit(sp.valid))
-                    buf_store(lane_bit(sp.bmask) ? v[s] : (ST)0, rs, voff,
+                    buf_store(lane_bit(sp.bmask) ? (ST)v[s] : (ST)0, rs, voff,
                               sp.word * 64 * (int)sizeof(ST));
             }
         }
@@ -242,13 +245,13 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
                 if (w >= NF) w -= NF;
                 ST x = buf_load<ST>(rs, voff, w * 64 * (int)sizeof(ST));
                 if (s == 0) x = lane_bit(m0) ? x : (ST)0;
-                v[s] = x;
+                v[s] = (T)x;
             } else {
                 SpecSlot sp = special_slot(opaque(nwaves * NR + wave * K) + (s - NR), NF, N, g,
                                            self_full, sw, self_bit);
                 ST x = (ST)0;
                 if (lane_bit(sp.bmask)) x = buf_load<ST>(rs, voff, sp.word * 64 * (int)sizeof(ST));
-                v[s] = x;
+                v[s] = (T)x;
             }
         }
     };
@@ -279,7 +282,7 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
     const bool fresh = a.l0 < 0;
     if (fresh) {
 #pragma unroll
-        for (int s = 0; s < NSLOT; ++s) v[s] = (ST)0;
+        for (int s = 0; s < NSLOT; ++s) v[s] = (T)0;
     } else {
         base = log_scale[r];
         load_state();
