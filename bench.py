@@ -33,6 +33,7 @@ VALU_PEAK = 256 * 4 * 32 * 2.4e9
 # FP64 vector peak: 78.6 TFLOP/s, i.e. 39.3e12 FP64 FMA lane-operations/s.
 VALU_PEAK_F64 = 256 * 4 * 16 * 2.4e9
 OPS_PER_CELL = 4                  # emission select, FMA, MUL, ADD per cell per direction
+SWEEP_CHUNK = 4096                # variants per sweep launch (the library splits longer sweeps)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_bwd_fp32_c2_traffic.txt")
 SWEEP_SOURCES = ["ls_sweep.h", "ls_device.h", "ls_internal.h", "ls_sweep_f32_bwd.hip"]
 
@@ -178,10 +179,12 @@ def main():
 
     # posterior error of the FP32 sweep against FP64 (GPU) and against the
     # FP64 oracle, on seeded recipients (outside the timed region)
-    rec = seeded_recipients(N, args.err_recipients, seed=2212)
-    p32 = ls.decode(model, targets, "fp32", recipients=rec, want=("P",))["P"]
+    rec = seeded_recipients(N, max(args.err_recipients, 1), seed=2212)
+    p32 = None
+    if args.err_recipients > 0:
+        p32 = ls.decode(model, targets, "fp32", recipients=rec, want=("P",))["P"]
     err = {}
-    if not args.no_fp64:
+    if p32 is not None and not args.no_fp64:
         out64 = ls.decode(model, targets, "fp64", recipients=rec, want=("P",))
         p64 = out64["P"]
         err["max_posterior_err_fp32_vs_fp64"] = float((p32.double() - p64).abs().max().item())
@@ -194,7 +197,8 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         nthreads = oracle.default_threads()
-        sample = rec[: nthreads]
+        # about 10-20 s of oracle work on the host's cores
+        sample = seeded_recipients(N, 3 * nthreads, seed=2212)
         t0 = time.perf_counter()
         ref = oracle.run_pass(x["H"], N, L, x["rho"], x["mu"], sample, targets, want=("P",),
                               nthreads=nthreads)
@@ -203,22 +207,27 @@ def main():
         cpu = {"value": cpu_rate, "unit": "cells/s", "cores": int(nthreads), "kind": "oracle",
                "sample": f"{len(sample)} seeded recipients x all {N} donors x all {L} variants, "
                          f"forward+backward+posteriors at {T} targets, FP64 C, {dt_cpu:.1f} s"}
-        pos = np.searchsorted(rec, sample)
-        err["max_posterior_err_fp32_vs_oracle"] = float(
-            np.abs(p32[:, pos, :].double().cpu().numpy() - ref["P"]).max())
+        if p32 is not None:
+            p_s = ls.decode(model, targets, "fp32", recipients=sample, want=("P",))["P"]
+            err["max_posterior_err_fp32_vs_oracle"] = float(
+                np.abs(p_s.double().cpu().numpy() - ref["P"]).max())
+            del p_s
         log(f"oracle: {cpu_rate:.3e} cells/s on {nthreads} threads ({dt_cpu:.1f}s)")
     del p32
 
-    # roofline of the dominant kernel (the backward sweep: one launch per step)
+    # roofline of the dominant kernel: the backward sweep, launched once per
+    # SWEEP_CHUNK variants; per-launch figures are averages over the sweep
     shape = ls.kernel_shape(N, "fp32")
+    launches = -(-(L - 1) // SWEEP_CHUNK)
     bwd_s = r32["bwd_ms"] / 1e3
     achieved = OPS_PER_CELL * cells / bwd_s
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                 "unit": "TOP/s", "frac": achieved / VALU_PEAK,
                 "traffic": measured_traffic(shape),
                 "kernel": f"sweep_kernel<PrecF32,{shape[0]},1> (backward)",
-                "ops_per_cell": OPS_PER_CELL, "cells_per_launch": cells,
-                "launch_ms": r32["bwd_ms"]}
+                "ops_per_cell": OPS_PER_CELL, "launches_per_sweep": launches,
+                "cells_per_launch": cells / launches,
+                "launch_ms": r32["bwd_ms"] / launches}
     line = {
         "metric": "LS fwd+bwd cell updates/s (N^2 L / s), FP32-scaled sweep",
         "value": value,
