@@ -82,6 +82,15 @@ def load():
         raise RuntimeError(
             f"{LIB_PATH} is missing: build it with paper_2212_11403_amd.build.build() "
             "(the GPU path has no CPU fallback)")
+    # The binding hands torch device memory and streams to the library, so
+    # both must use one HIP runtime. torch ships its own libamdhip64.so.7;
+    # once it is loaded it also satisfies libls.so's dependency. Opened
+    # first, libls.so would map the system runtime and torch would then map
+    # its own beside it, and pointers from one are invalid in the other.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P, I32, I64, U64, SZ, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                ctypes.c_size_t, ctypes.c_double)

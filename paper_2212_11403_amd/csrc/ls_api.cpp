@@ -219,6 +219,13 @@ ls_status check_table(const ls_table *t, const ls_model *m, int dir) {
 
 }  // namespace
 
+// hipGetLastError() reports the last error of any HIP runtime call made on
+// the calling thread, including calls by other libraries that handled their
+// own failure (a framework probing devices, for instance). Every entry point
+// that launches clears it first, so the check after its own launches sees
+// only those launches.
+static inline void clear_stale_hip_error() { (void)hipGetLastError(); }
+
 extern "C" {
 
 size_t ls_model_workspace_bytes(int32_t N, int32_t L) {
@@ -227,6 +234,7 @@ size_t ls_model_workspace_bytes(int32_t N, int32_t L) {
 }
 
 ls_status ls_model_init(ls_model *m, void *workspace, size_t ws_bytes, void *stream) {
+    clear_stale_hip_error();
     if (!m || !m->H || m->N < 2 || m->L < 1) return LS_ERR_ARG;
     if (m->stride_words < (m->N + 31) / 32 || (m->stride_words & 1)) return LS_ERR_ARG;
     if (!(m->mu >= 0.0 && m->mu <= 1.0)) return LS_ERR_ARG;
@@ -265,6 +273,7 @@ ls_status ls_model_init(ls_model *m, void *workspace, size_t ws_bytes, void *str
 ls_status ls_table_init(ls_table *t, int32_t direction, ls_precision prec, void *state,
                         double *log_scale, uint32_t *status, const int32_t *recipients,
                         int32_t R, void *stream) {
+    clear_stale_hip_error();
     if (!t || (direction != 0 && direction != 1) || !valid_prec(prec) || !state || !log_scale ||
         !status || !recipients || R < 1)
         return LS_ERR_ARG;
@@ -281,6 +290,7 @@ ls_status ls_table_init(ls_table *t, int32_t direction, ls_precision prec, void 
 }
 
 ls_status ls_table_copy(ls_table *dst, const ls_table *src, int32_t N, void *stream) {
+    clear_stale_hip_error();
     if (!dst || !src || N < 2 || !dst->state || !src->state || !dst->log_scale ||
         !src->log_scale || !dst->status || !src->status)
         return LS_ERR_ARG;
@@ -305,6 +315,7 @@ ls_status ls_table_copy(ls_table *dst, const ls_table *src, int32_t N, void *str
 
 ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t *targets,
                      int32_t T, const void *bsnap, void *P, void *E, void *stream) {
+    clear_stale_hip_error();
     ls_status s = check_model(m);
     if (s != LS_OK) return s;
     if ((s = check_table(fwd, m, 0)) != LS_OK) return s;
@@ -358,6 +369,7 @@ ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t 
 
 ls_status ls_backward(ls_table *bck, const ls_model *m, int32_t t, const int32_t *targets,
                       int32_t T, void *bsnap, void *stream) {
+    clear_stale_hip_error();
     ls_status s = check_model(m);
     if (s != LS_OK) return s;
     if ((s = check_table(bck, m, 1)) != LS_OK) return s;
@@ -402,6 +414,7 @@ ls_status ls_backward(ls_table *bck, const ls_model *m, int32_t t, const int32_t
 
 ls_status ls_posterior_distance(const ls_table *fwd, const ls_table *bck, const ls_model *m,
                                 void *P, void *E, void *stream) {
+    clear_stale_hip_error();
     ls_status s = check_model(m);
     if (s != LS_OK) return s;
     if ((s = check_table(fwd, m, 0)) != LS_OK) return s;
@@ -420,6 +433,7 @@ ls_status ls_posterior_distance(const ls_table *fwd, const ls_table *bck, const 
 
 ls_status ls_distance_symmetrise(const void *E, void *D, int32_t N, int32_t T,
                                  ls_precision prec, void *stream) {
+    clear_stale_hip_error();
     if (!E || !D || N < 1 || T < 0 || !valid_prec(prec)) return LS_ERR_ARG;
     return dev(lsk::launch_symmetrise(E, D, N, T, prec == LS_FP64, as_stream(stream)));
 }
@@ -432,6 +446,7 @@ size_t ls_loglik_grad_workspace_bytes(const ls_model *m, int32_t R, ls_precision
 ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R,
                          ls_precision prec, double *loglik, double *pac, double *grad_rho,
                          double *grad_mu, void *workspace, size_t ws_bytes, void *stream) {
+    clear_stale_hip_error();
     ls_status s = check_model(m);
     if (s != LS_OK) return s;
     if (R < 1 || !valid_prec(prec) || !pac) return LS_ERR_ARG;
@@ -485,6 +500,7 @@ ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R
 }
 
 ls_status ls_status_check(const uint32_t *status, int32_t R, void *stream) {
+    clear_stale_hip_error();
     if (!status || R < 1) return LS_ERR_ARG;
     std::vector<uint32_t> h((size_t)R);
     hipStream_t st = as_stream(stream);

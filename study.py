@@ -1,0 +1,262 @@
+"""Measurements on the workloads other than the benchmark's (one JSON line each).
+
+    python study.py c4   gradient of the PAC log-likelihood (N = 2,000,
+                         L = 50,000): time per gradient in FP32 and FP64,
+                         VALU and HBM rooflines of the pass, FP32 adjoint vs
+                         the FP64 oracle score on seeded recipients and vs
+                         central differences of the FP64 GPU PAC
+    python study.py c3   precision study (N = 50,000, L = 20,000, rare-variant
+                         mosaic, 20 targets): FP32 and FP16-stored posteriors
+                         and log-likelihoods vs the FP64 oracle on seeded
+                         recipients, and the decode time of all recipients
+    python study.py c5   the share of one GPU of the large workload
+                         (N = 100,000, L = 10,000, 5 targets): recipients
+                         [0, 12,500) against all 100,000 donors, FP32 decode
+                         time, E-write bandwidth, posterior error vs the oracle
+
+Inputs are the seeded synthetic workloads of `lsinputs`; the oracle runs on
+the host's cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+VALU_PEAK = 256 * 4 * 32 * 2.4e9      # FP32 lane-operations/s (157.3 TFLOP/s / 2)
+VALU_PEAK_F64 = 256 * 4 * 16 * 2.4e9  # FP64 lane-operations/s (78.6 TFLOP/s / 2)
+HBM_PEAK = 8.0e12                     # bytes/s
+
+
+def log(msg):
+    print(f"[study] {msg}", file=sys.stderr, flush=True)
+
+
+def events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def study_c4(args):
+    import torch
+
+    import oracle
+    import paper_2212_11403_amd as ls
+    from lsinputs import make_inputs, seeded_recipients
+
+    x = make_inputs("c4")
+    N, L, rho, mu = x["N"], x["L"], x["rho"], x["mu"]
+    model = ls.Model(x["H"], N, rho, mu)
+    out = {"study": "c4 gradient", "N": N, "L": L, "recipients": N}
+    res = {}
+    for prec in ("fp32", "fp64"):
+        ls.loglik_grad(model, None, prec, grad=True)  # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = events()
+        e0.record()
+        g = ls.loglik_grad(model, None, prec, grad=True)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        e0.record()
+        ls.loglik_grad(model, None, prec, grad=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_ll = e0.elapsed_time(e1)
+        res[prec] = g
+        cells = float(N) * N * L
+        seg = int(np.ceil(np.sqrt(L)))
+        esz = 4 if prec == "fp32" else 8
+        # forward with checkpoints (4 ops/cell), per segment a forward
+        # recompute (4) and the adjoint pass (12: select, fma, mul, add for
+        # the backward vector; fma, add, fma, select+fma for d, Sa, M)
+        ops = 20.0 * cells
+        # segment buffer written by the recompute and read by the adjoint,
+        # plus checkpoints written once and read once
+        hbm = 2.0 * cells * esz + 2.0 * (L / seg) * N * N * esz
+        peak = VALU_PEAK if prec == "fp32" else VALU_PEAK_F64
+        out[prec] = {"gradient_ms": ms, "loglik_only_ms": ms_ll,
+                     "cells_per_s": cells / (ms / 1e3),
+                     "valu_frac": ops / (ms / 1e3) / peak,
+                     "hbm_frac": hbm / (ms / 1e3) / HBM_PEAK,
+                     "pac": float(g["pac"].item())}
+        log(f"{prec}: gradient {ms:.1f} ms, log-likelihood only {ms_ll:.1f} ms")
+    g32, g64 = res["fp32"], res["fp64"]
+    gr32 = g32["grad_rho"].cpu().numpy()
+    gr64 = g64["grad_rho"].cpu().numpy()
+    out["fp32_vs_fp64_grad_rho_normwise"] = float(np.abs(gr32 - gr64).max() / np.abs(gr64).max())
+    out["fp32_vs_fp64_grad_mu_rel"] = float(abs(g32["grad_mu"].item() - g64["grad_mu"].item())
+                                           / abs(g64["grad_mu"].item()))
+    # oracle score on seeded recipients (full L)
+    rec = seeded_recipients(N, args.recipients, seed=404)
+    t0 = time.perf_counter()
+    ref = oracle.run_gradient(x["H"], N, L, rho, mu, rec)
+    dt = time.perf_counter() - t0
+    gsub = ls.loglik_grad(model, rec, "fp32", grad=True)
+    gsub64 = ls.loglik_grad(model, rec, "fp64", grad=True)
+    rg = ref["grad_rho"].sum(axis=0)
+    for name, gg in (("fp32", gsub), ("fp64", gsub64)):
+        out[f"{name}_vs_oracle_grad_rho_normwise"] = float(
+            np.abs(gg["grad_rho"].cpu().numpy() - rg).max() / np.abs(rg).max())
+        out[f"{name}_vs_oracle_grad_mu_rel"] = float(
+            abs(gg["grad_mu"].item() - ref["grad_mu"].sum()) / abs(ref["grad_mu"].sum()))
+        out[f"{name}_vs_oracle_pac_rel"] = float(
+            abs(gg["pac"].item() - ref["loglik"].sum()) / abs(ref["loglik"].sum()))
+    out["oracle_recipients"] = len(rec)
+    out["oracle_seconds"] = dt
+    # central differences of the FP64 GPU PAC (all recipients), h = 1e-6 rho_l
+    rng = np.random.default_rng(7)
+    picks = rng.choice(np.nonzero(rho >= 1e-4)[0], args.fd, replace=False)
+    worst = 0.0
+    gmax = np.abs(gr32).max()
+    for l in picks:
+        h = 1e-6 * rho[l]
+        rp, rm = rho.copy(), rho.copy()
+        rp[l] += h
+        rm[l] -= h
+        fp = ls.loglik_grad(ls.Model(x["H"], N, rp, mu), None, "fp64", grad=False)["pac"].item()
+        fm = ls.loglik_grad(ls.Model(x["H"], N, rm, mu), None, "fp64", grad=False)["pac"].item()
+        fd = (fp - fm) / (2 * h)
+        worst = max(worst, abs(fd - gr32[l]) / gmax)
+    out["fp32_vs_fd_normwise_max"] = worst
+    out["fd_components"] = int(len(picks))
+    print(json.dumps(out), flush=True)
+
+
+def _decode_errors(ls, model, x, rec, targets, prec, ref):
+    r = ls.decode(model, targets, prec, recipients=rec, want=("P", "E"))
+    P = r["P"].double().cpu().numpy()
+    E = r["E"].double().cpu().numpy()
+    ll = r["fwd"].log_scale.cpu().numpy()
+    both = (ref["P"] >= 1e-4)
+    return {"max_abs_posterior_err": float(np.abs(P - ref["P"]).max()),
+            "max_rel_loglik_err": float(np.max(np.abs(ll - ref["llf"]) / np.abs(ref["llf"]))),
+            "max_abs_half_distance_err_p_ge_1e-4": float(np.abs(E - ref["E"])[both].max()),
+            "nonfinite": int(ls.status_check(r["fwd"]))}
+
+
+def study_c3(args):
+    import torch
+
+    import oracle
+    import paper_2212_11403_amd as ls
+    from lsinputs import make_inputs, seeded_recipients
+
+    x = make_inputs("c3")
+    N, L, targets = x["N"], x["L"], x["targets"]
+    model = ls.Model(x["H"], N, x["rho"], x["mu"])
+    rec = seeded_recipients(N, args.recipients, seed=3)
+    t0 = time.perf_counter()
+    ref = oracle.run_pass(x["H"], N, L, x["rho"], x["mu"], rec, targets, want=("P", "E"))
+    dt = time.perf_counter() - t0
+    out = {"study": "c3 precision", "N": N, "L": L, "targets": len(targets),
+           "oracle_recipients": len(rec), "oracle_seconds": dt}
+    for prec in ("fp32", "f16"):
+        out[prec] = _decode_errors(ls, model, x, rec, targets, prec, ref)
+        out[prec]["shape"] = list(ls.kernel_shape(N, prec))
+        # decode of all recipients (posteriors not kept: the forward stages
+        # alpha into E and writes half distances), in windows that fit HBM
+        win = args.window
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for lo in range(0, N, win):
+            sub = np.arange(lo, min(N, lo + win), dtype=np.int32)
+            ls.decode(model, targets, prec, recipients=sub, want=("E",))
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t1
+        out[prec]["decode_all_seconds"] = sec
+        out[prec]["cells_per_s"] = float(N) * N * L / sec
+        log(f"{prec}: {out[prec]}")
+    print(json.dumps(out), flush=True)
+
+
+def study_c5(args):
+    import torch
+
+    import oracle
+    import paper_2212_11403_amd as ls
+    from lsinputs import make_inputs, seeded_recipients
+
+    x = make_inputs("c5")
+    N, L, targets = x["N"], x["L"], x["targets"]
+    T = len(targets)
+    model = ls.Model(x["H"], N, x["rho"], x["mu"])
+    share = np.arange(0, N // 8, dtype=np.int32)
+    R = len(share)
+    out = {"study": "c5 one-GPU share", "N": N, "L": L, "targets": T, "recipients": R,
+           "shape": list(ls.kernel_shape(N, "fp32"))}
+    fwd = ls.Table(model, 0, "fp32", share)
+    bck = ls.Table(model, 1, "fp32", share)
+    bsnap = torch.empty((T, R, N), dtype=torch.float32, device="cuda")
+    E = torch.empty((T, R, N), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    ls.backward(bck, model, 0, targets, bsnap)
+    ev[1].record(stream)
+    ls.forward(fwd, model, L - 1, targets, bsnap, None, E)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    bwd_ms, fwd_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    cells = float(R) * N * L
+    out["backward_ms"] = bwd_ms
+    out["forward_and_posterior_ms"] = fwd_ms
+    out["cells_per_s"] = cells / ((bwd_ms + fwd_ms) / 1e3)
+    out["backward_valu_frac"] = 4 * cells / (bwd_ms / 1e3) / VALU_PEAK
+    # a forward sweep without targets: the difference is the staging of
+    # alpha at the targets and the posterior/half-distance rows (alpha and
+    # beta read twice each, E written once: 20 B per entry)
+    fwd2 = ls.Table(model, 0, "fp32", share)
+    ev[0].record(stream)
+    ls.forward(fwd2, model, L - 1)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    plain_ms = ev[0].elapsed_time(ev[1])
+    out["forward_without_targets_ms"] = plain_ms
+    out["target_outputs_ms"] = fwd_ms - plain_ms
+    out["target_outputs_GBps"] = 20.0 * T * R * N / ((fwd_ms - plain_ms) / 1e3) / 1e9
+    status = ls.status_check(fwd)
+    out["nonfinite"] = int(status)
+    rec = seeded_recipients(R, args.recipients, seed=5)
+    t0 = time.perf_counter()
+    ref = oracle.run_pass(x["H"], N, L, x["rho"], x["mu"], rec, targets, want=("P",))
+    out["oracle_seconds"] = time.perf_counter() - t0
+    out["oracle_recipients"] = len(rec)
+    r = ls.decode(model, targets, "fp32", recipients=rec, want=("P",))
+    out["max_abs_posterior_err_vs_oracle"] = float(
+        np.abs(r["P"].double().cpu().numpy() - ref["P"]).max())
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("which", choices=["c3", "c4", "c5"])
+    ap.add_argument("--recipients", type=int, default=None,
+                    help="seeded recipients checked against the oracle")
+    ap.add_argument("--fd", type=int, default=16, help="finite-difference components (c4)")
+    ap.add_argument("--window", type=int, default=12_500, help="recipients per decode (c3)")
+    args = ap.parse_args()
+    import paper_2212_11403_amd as ls
+    ls.load()
+    if args.which == "c4":
+        args.recipients = args.recipients or 64
+        study_c4(args)
+    elif args.which == "c3":
+        args.recipients = args.recipients or 128
+        study_c3(args)
+    else:
+        args.recipients = args.recipients or 32
+        study_c5(args)
+
+
+if __name__ == "__main__":
+    main()

@@ -178,6 +178,22 @@ def test_forced_wide_shapes(ls, prec, N, ns, nw):
         assert np.max(np.abs(_np(r["fwd"].log_scale) - ref["llf"]) / np.abs(ref["llf"])) <= 1e-5
 
 
+def test_stale_hip_error_is_not_reported(ls):
+    """A failed HIP call made by someone else on this thread (here an invalid
+    device ordinal, rejected on the host) must not surface as an error of the
+    next library call."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    count = ctypes.c_int(0)
+    assert hip.hipGetDeviceCount(ctypes.byref(count)) == 0
+    assert hip.hipSetDevice(count.value + 5) != 0  # leaves a last-error behind
+    N, L = 70, 12
+    H, rho, mu = _random_case(N, L, seed=9)
+    m = ls.Model(H, N, rho, mu)
+    r = ls.decode(m, [3, 7], "fp64", want=("P",))
+    assert np.all(np.isfinite(_np(r["P"])))
+
+
 def test_recipient_subset_equals_full(ls, c1):
     """Windows of recipients give the same columns (tables are independent
     HMMs, section 3.9)."""
