@@ -97,7 +97,8 @@ typedef struct {
 } ls_model;
 
 /* Device bytes of the workspace ls_model_init lays the internal haplotype
- * rows into (about 2 N L / 8 bytes). */
+ * rows (about 2 N L / 8 bytes) and the per-variant FP32 transition
+ * coefficients of the sweeps (32 L bytes) into. */
 size_t ls_model_workspace_bytes(int32_t N, int32_t L);
 
 /* Validates the inputs, computes the hash and builds the internal rows in

@@ -34,6 +34,13 @@ int64_t hr_stride_for(int32_t N) {
     return (need + 7) / 8 * 8;
 }
 
+// Byte offset of the coefficient tables in the model workspace (after the
+// internal rows, 256-byte aligned).
+size_t coef_offset_bytes(int32_t N, int32_t L) {
+    const size_t rows = (size_t)L * (size_t)hr_stride_for(N) * sizeof(uint64_t);
+    return (rows + 255) / 256 * 256;
+}
+
 uint64_t fnv1a(uint64_t h, const void *data, size_t n) {
     const unsigned char *p = static_cast<const unsigned char *>(data);
     for (size_t i = 0; i < n; ++i) {
@@ -153,6 +160,15 @@ void fill_scalars(SweepArgs &a, const ls_model *m, int prec, int dir) {
     }
 }
 
+// The coefficient table of a precision and direction (FP32 arithmetic), or
+// null for the FP64 sweep, which forms its coefficients per variant.
+const float *coef_table(const ls_model *m, int prec, int dir) {
+    if (prec == LS_FP64) return nullptr;
+    const int k = (prec == LS_FP32 ? lsk::kCoefF32Fwd : lsk::kCoefF16Fwd) + (dir ? 1 : 0);
+    const char *base = reinterpret_cast<const char *>(m->Hr) + coef_offset_bytes(m->N, m->L);
+    return reinterpret_cast<const float *>(base) + (size_t)k * 2 * (size_t)m->L;
+}
+
 hipError_t launch_sweep(int prec, int dir, const SweepPtrs &p, const SweepArgs &a, Shape sh,
                         hipStream_t st) {
     if (prec == LS_FP64)
@@ -230,7 +246,7 @@ extern "C" {
 
 size_t ls_model_workspace_bytes(int32_t N, int32_t L) {
     if (N < 2 || L < 1) return 0;
-    return (size_t)L * (size_t)hr_stride_for(N) * sizeof(uint64_t);
+    return coef_offset_bytes(N, L) + (size_t)lsk::kCoefTables * 2 * (size_t)L * sizeof(float);
 }
 
 ls_status ls_model_init(ls_model *m, void *workspace, size_t ws_bytes, void *stream) {
@@ -261,6 +277,17 @@ ls_status ls_model_init(ls_model *m, void *workspace, size_t ws_bytes, void *str
     const int64_t hs = hr_stride_for(m->N);
     uint64_t *Hr = static_cast<uint64_t *>(workspace);
     hipError_t e = lsk::launch_repack(m->H, m->stride_words, m->N, m->L, Hr, hs, st);
+    if (e != hipSuccess) return LS_ERR_DEVICE;
+    lsk::CoefScalars cs;
+    for (int k = 0; k < lsk::kCoefTables; ++k) {
+        SweepArgs sa;
+        fill_scalars(sa, m, k < 2 ? LS_FP32 : LS_FP32_F16STORE, k & 1);
+        cs.cnum[k] = sa.cnum;
+        cs.bmul[k] = sa.bmul;
+    }
+    float *coef = reinterpret_cast<float *>(static_cast<char *>(workspace) +
+                                            coef_offset_bytes(m->N, m->L));
+    e = lsk::launch_coef_tables(m->L > 1 ? m->rho : nullptr, m->L, cs, coef, st);
     if (e != hipSuccess) return LS_ERR_DEVICE;
     m->hash = h;
     m->Hr = Hr;
@@ -349,6 +376,7 @@ ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t 
     SweepPtrs p;
     p.Hr = m->Hr;
     p.rho = m->L > 1 ? m->rho : reinterpret_cast<const double *>(m->Hr);  // only a discarded load when L == 1
+    p.coef = coef_table(m, fwd->prec, 0);
     p.recipients = fwd->recipients;
     p.state = fwd->state;
     p.log_scale = fwd->log_scale;
@@ -400,6 +428,7 @@ ls_status ls_backward(ls_table *bck, const ls_model *m, int32_t t, const int32_t
     SweepPtrs p;
     p.Hr = m->Hr;
     p.rho = m->L > 1 ? m->rho : reinterpret_cast<const double *>(m->Hr);  // only a discarded load when L == 1
+    p.coef = coef_table(m, bck->prec, 1);
     p.recipients = bck->recipients;
     p.state = bck->state;
     p.log_scale = bck->log_scale;
@@ -485,6 +514,7 @@ ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R
     std::memset(&ga, 0, sizeof ga);
     ga.Hr = m->Hr;
     ga.rho = m->L > 1 ? m->rho : reinterpret_cast<const double *>(m->Hr);
+    ga.coef_fwd32 = coef_table(m, LS_FP32, 0);
     ga.recipients = rec;
     ga.hr_stride = m->hr_stride;
     ga.N = m->N;

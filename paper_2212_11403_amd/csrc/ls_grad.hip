@@ -339,6 +339,7 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
         SweepPtrs p;
         p.Hr = ga.Hr;
         p.rho = ga.rho;
+        p.coef = prec == 0 ? nullptr : ga.coef_fwd32;
         p.recipients = ga.recipients;
         p.state = state;
         p.log_scale = lsc;

@@ -21,6 +21,8 @@ constexpr uint32_t kFlagBadRecipient = 2u;  // LS_FLAG_BAD_RECIPIENT
 struct SweepPtrs {
     const uint64_t *Hr;         // [L][hr_stride] internal rows (see ls_model_init)
     const double *rho;          // [L-1]
+    const float *coef;          // [L][2] coefficient table of the precision and
+                                // direction (FP32 arithmetic), else null
     const int32_t *recipients;  // [R]
     void *state;                // table state [R][N]
     double *log_scale;          // [R]
@@ -109,7 +111,22 @@ LS_DECLARE_LAUNCH(f16, bwd)
 // Special (boundary) slots per wave for a given slot count.
 __host__ __device__ constexpr int special_slots(int nslot) { return nslot < 4 ? nslot : 4; }
 
+// Per-variant coefficients of the FP32 sweeps, kept in the model workspace
+// after the internal rows: kCoefTables tables of L pairs (A_l, B_l), with
+// c = A_l / S and b = B_l in the sweep's update v <- theta (c v + b):
+//   forward:  l = 0: (0, bmul); l >= 1: ((1 - rho_{l-1}) cnum, rho_{l-1} bmul)
+//   backward: l <= L-2: ((1 - rho_l) cnum, rho_l bmul); l = L-1: (0, 0), unused
+// Each product is formed in FP64 and rounded once to FP32, which is what the
+// sweep computed per variant before, so results do not change.
+enum { kCoefF32Fwd = 0, kCoefF32Bwd = 1, kCoefF16Fwd = 2, kCoefF16Bwd = 3, kCoefTables = 4 };
+struct CoefScalars {
+    double cnum[kCoefTables];
+    double bmul[kCoefTables];
+};
+
 // Miscellaneous kernels (ls_misc.hip).
+hipError_t launch_coef_tables(const double *rho, int32_t L, const CoefScalars &cs, float *out,
+                              hipStream_t st);
 hipError_t launch_repack(const uint32_t *H, int64_t stride_words, int32_t N, int32_t L,
                          uint64_t *Hr, int64_t hr_stride, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
@@ -145,6 +162,7 @@ size_t grad_workspace_bytes(int32_t N, int32_t L, int32_t R, int prec, GradLayou
 struct GradArgs {
     const uint64_t *Hr;
     const double *rho;
+    const float *coef_fwd32;  // FP32 forward coefficient table
     const int32_t *recipients;
     int64_t hr_stride;
     int32_t N, L, NF, R;

@@ -43,6 +43,42 @@ hipError_t launch_repack(const uint32_t *H, int64_t stride_words, int32_t N, int
     return hipGetLastError();
 }
 
+// One thread per variant writes its pair in all coefficient tables.
+__global__ void __launch_bounds__(256)
+coef_tables_kernel(const double *__restrict__ rho, int32_t L, CoefScalars cs,
+                   float *__restrict__ out) {
+#pragma clang fp contract(off)
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= L) return;
+#pragma unroll
+    for (int k = 0; k < kCoefTables; ++k) {
+        double A = 0.0, B = 0.0;
+        if ((k & 1) == 0) {  // forward: variant l uses rho_{l-1}
+            if (l == 0) {
+                B = cs.bmul[k];
+            } else {
+                const double rr = rho[l - 1];
+                A = (1.0 - rr) * cs.cnum[k];
+                B = rr * cs.bmul[k];
+            }
+        } else if (l <= L - 2) {  // backward: variant l uses rho_l
+            const double rr = rho[l];
+            A = (1.0 - rr) * cs.cnum[k];
+            B = rr * cs.bmul[k];
+        }
+        out[(int64_t)k * 2 * L + 2 * l] = (float)A;
+        out[(int64_t)k * 2 * L + 2 * l + 1] = (float)B;
+    }
+}
+
+hipError_t launch_coef_tables(const double *rho, int32_t L, const CoefScalars &cs, float *out,
+                              hipStream_t st) {
+    if (L < 1) return hipSuccess;
+    hipLaunchKernelGGL(coef_tables_kernel, dim3((unsigned)((L + 255) / 256)), dim3(256), 0, st,
+                       rho, L, cs, out);
+    return hipGetLastError();
+}
+
 __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)

@@ -70,7 +70,7 @@ template <class PT, int NSLOT, int DIR>
 __global__ void __launch_bounds__(64 * max_waves_for(NSLOT, PT::vgpr_per_slot))
 __attribute__((amdgpu_waves_per_eu(sweep_waves_per_simd(NSLOT, PT::vgpr_per_slot))))
 sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
-             const int32_t *__restrict__ recipients, typename PT::ST *__restrict__ state,
+             const float *__restrict__ coef, const int32_t *__restrict__ recipients, typename PT::ST *__restrict__ state,
              double *__restrict__ log_scale, uint32_t *__restrict__ status,
              typename PT::IO *__restrict__ snap, const SweepArgs a) {
     // No contraction: the column sums add the rounded entries, exactly as
@@ -147,10 +147,11 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
         return (s < NR) ? row[reg_base + s] : row[spec_off[s - NR]];
     };
     // v <- theta^l (.) (c v + b); returns this lane's partial sum
-    auto step = [&](int l, uint64_t sw_bits, T c, T b) __attribute__((always_inline)) -> T {
+    auto step = [&](int l, uint64_t sw_bits, T c, T b_s) __attribute__((always_inline)) -> T {
         const uint64_t *row = Hr + (int64_t)l * a.hr_stride;
         T ta, tb;
         thetas(sw_bits, ta, tb);
+        const T b = in_vgpr(b_s);
         T acc0 = 0, acc1 = 0;
 #pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
@@ -260,12 +261,34 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
         store_row(dst, (T)a.inv_kappa);
         ++kt;
     };
-    // c = num / S in the sweep precision: FP64 divides (correctly rounded),
+    // (A_l, B_l) of variant l, with c = A_l / S and b = B_l. FP32 sweeps read
+    // them from the model's coefficient table (formed in FP64, rounded once);
+    // the FP64 sweep forms them here. Forward variant l uses rho_{l-1} (and
+    // at l = 0 gives c = 0, b = kappa / (N-1), i.e. alpha^0); backward
+    // variant l uses rho_l.
+    auto coefs_at = [&](int l, T &A, T &B) __attribute__((always_inline)) {
+        if constexpr (sizeof(T) == 4) {
+            A = coef[2 * l];
+            B = coef[2 * l + 1];
+        } else if constexpr (DIR == 0) {
+            // the load is unconditional: a branch here costs registers
+            const double r0 = rho[l > 0 ? l - 1 : 0];
+            const double rr = l > 0 ? r0 : 1.0;
+            const double keep = l > 0 ? 1.0 : 0.0;
+            A = keep * (1.0 - rr) * a.cnum;
+            B = rr * a.bmul;
+        } else {
+            const double rr = rho[l];
+            A = (1.0 - rr) * a.cnum;
+            B = rr * a.bmul;
+        }
+    };
+    // c = A / S in the sweep precision: FP64 divides (correctly rounded),
     // FP32 multiplies by the hardware reciprocal (within 1 ulp), which is
     // below the rounding of the FP32 update itself
-    auto coef = [&](double num, T sum) __attribute__((always_inline)) -> T {
-        if constexpr (sizeof(T) == 4) return (T)num * __builtin_amdgcn_rcpf(sum);
-        else return (T)num / sum;
+    auto coef_c = [&](T A, T sum) __attribute__((always_inline)) -> T {
+        if constexpr (sizeof(T) == 4) return A * __builtin_amdgcn_rcpf(sum);
+        else return A / sum;
     };
     auto account = [&](T sum) __attribute__((always_inline)) {
         int e;
@@ -303,25 +326,22 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
             }
             S = block_sum<MAXW>(acc0 + acc1, red, parity, wave, nwaves);
         }
-        // rho and the recipient's own word are read one variant ahead, so
-        // their latency overlaps the previous step
+        // the coefficients and the recipient's own word are read one variant
+        // ahead, so their latency overlaps the previous step
         const int lmax = a.L - 1;
         for (;;) {
             const int lend = kt < a.nt ? a.tgt_l[kt] : a.t;
-            double r_nx = rho[l > 0 ? l - 1 : 0];
+            T A_nx, B_nx;
+            coefs_at(l <= lmax ? l : lmax, A_nx, B_nx);
             uint64_t w_nx = self_word(l <= lmax ? l : lmax);
             for (; l <= lend; ++l) {
-                // at l = 0: c = 0 and b = kappa/(N-1), which gives alpha^0
-                // (the loads are unconditional: a branch here costs registers)
-                const double r0 = r_nx;
+                const T A = A_nx, B = B_nx;
                 const uint64_t wb = w_nx;
                 const int ln = l < lmax ? l + 1 : lmax;
-                r_nx = rho[ln > 0 ? ln - 1 : 0];
+                coefs_at(ln, A_nx, B_nx);
                 w_nx = self_word(ln);
-                const double rr = l > 0 ? r0 : 1.0;
-                const double keep = l > 0 ? 1.0 : 0.0;
-                const T c = coef(keep * (1.0 - rr) * a.cnum, S);
-                const T b = (T)(rr * a.bmul);
+                const T c = coef_c(A, S);
+                const T b = B;
                 T part = step(l, wb, c, b);
                 S = block_sum<MAXW>(part, red, parity, wave, nwaves);
                 account(S);
@@ -340,25 +360,28 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
             int l = lstart - 1;
             for (;;) {
                 const int lend = kt < a.nt ? a.tgt_l[kt] : a.t;
-                // rho and the recipient's own word are read one variant ahead
-                double r_nx = rho[l];
+                // the coefficients and the recipient's own word are read one
+                // variant ahead
+                T A_nx, B_nx;
+                coefs_at(l, A_nx, B_nx);
                 uint64_t w_nx = self_word(l);
                 for (; l > lend; --l) {
-                    const double rr = r_nx;
+                    const T A = A_nx, B = B_nx;
                     const uint64_t wb = w_nx;
                     const int ln = l > 0 ? l - 1 : 0;
-                    r_nx = rho[ln];
+                    coefs_at(ln, A_nx, B_nx);
                     w_nx = self_word(ln);
-                    const T c = coef((1.0 - rr) * a.cnum, S);
-                    const T b = (T)(rr * a.bmul);
+                    const T c = coef_c(A, S);
+                    const T b = B;
                     account(S);
                     part = step(l, wb, c, b);
                     S = block_sum<MAXW>(part, red, parity, wave, nwaves);
                 }
                 // l == lend: a target or the stopping variant; keep beta^l
-                const double rr = rho[l];
-                const T c = coef((1.0 - rr) * a.cnum, S);
-                const T b = (T)(rr * a.bmul);
+                T A, B;
+                coefs_at(l, A, B);
+                const T c = coef_c(A, S);
+                const T b = B;
                 account(S);
                 affine(c, b);
                 if (kt < a.nt && a.tgt_l[kt] == l) snapshot();

@@ -8,7 +8,7 @@ static hipError_t launch_one(const SweepPtrs &p, const SweepArgs &a, int nwaves,
     using PT = PrecF32;
     if (nwaves < 1 || nwaves > max_waves_for(NSLOT, PT::vgpr_per_slot)) return hipErrorInvalidValue;
     hipLaunchKernelGGL((sweep_kernel<PT, NSLOT, 1>), dim3(a.R), dim3(64 * nwaves), 0, st, p.Hr,
-                       p.rho, p.recipients, (PT::ST *)p.state, p.log_scale, p.status,
+                       p.rho, p.coef, p.recipients, (PT::ST *)p.state, p.log_scale, p.status,
                        (PT::IO *)p.snap, a);
     return hipGetLastError();
 }

@@ -56,9 +56,11 @@ def test_host_only_calls(lib):
     assert lib.ls_status_string(0).decode() == "ok"
     assert lib.ls_status_string(16).decode().startswith("a column sum")
     assert lib.ls_model_workspace_bytes(1, 10) == 0
-    # two copies of floor(N/64) words plus the partial word, padded to 64 B
-    assert lib.ls_model_workspace_bytes(200, 10) == 10 * 8 * 8
-    assert lib.ls_model_workspace_bytes(10000, 3) == 3 * 320 * 8
+    # internal rows: two copies of floor(N/64) words plus the partial word,
+    # padded to 64 B, the whole rounded up to 256 B; then four tables of L
+    # FP32 coefficient pairs
+    assert lib.ls_model_workspace_bytes(200, 10) == 768 + 4 * 10 * 2 * 4
+    assert lib.ls_model_workspace_bytes(10000, 3) == 7680 + 4 * 3 * 2 * 4
 
 
 def test_validation_errors_before_any_device_work(lib):
