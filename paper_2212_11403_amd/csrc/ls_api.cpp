@@ -191,8 +191,8 @@ hipError_t launch_sweep(int prec, int dir, const SweepPtrs &p, const SweepArgs &
 // stores round to half.
 constexpr int32_t kSweepChunk = 4096;
 
-hipError_t launch_sweep_chunked(int prec, int dir, const SweepPtrs &p, const SweepArgs &a,
-                                Shape sh, hipStream_t st) {
+hipError_t run_chunks(int prec, int dir, const SweepPtrs &p, const SweepArgs &a, Shape sh,
+                      hipStream_t st) {
     if (prec == LS_FP32_F16STORE) return launch_sweep(prec, dir, p, a, sh, st);
     SweepArgs c = a;
     int32_t l0 = a.l0;
@@ -221,6 +221,18 @@ hipError_t launch_sweep_chunked(int prec, int dir, const SweepPtrs &p, const Swe
         if (e != hipSuccess || tc == a.t) return e;
         l0 = tc;
     }
+}
+
+// A whole sweep over recipients [0, a.R), in chunks. (Splitting the
+// recipients over two streams, staggered or not, so that one half fills the
+// other's partly filled last round of workgroups, measured slower: the
+// concurrent launches cost more than the tail they fill.)
+hipError_t launch_sweep_chunked(int prec, int dir, const SweepPtrs &p, const SweepArgs &a,
+                                Shape sh, hipStream_t st) {
+    SweepArgs b = a;
+    b.r0 = 0;
+    b.nblk = a.R;
+    return run_chunks(prec, dir, p, b, sh, st);
 }
 
 ls_status check_table(const ls_table *t, const ls_model *m, int dir) {

@@ -356,6 +356,8 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
         a.l0 = l0;
         a.t = t;
         a.nt = nt;
+        a.r0 = 0;
+        a.nblk = ga.R;
         a.mu = ga.mu;
         a.kappa = 1.0;
         a.inv_kappa = 1.0;

@@ -36,6 +36,7 @@ struct SweepArgs {
     int32_t l0;           // current variant of the table (-1: not propagated)
     int32_t t;            // variant to stop at
     int32_t nt;           // number of targets visited, in travel order
+    int32_t r0, nblk;     // this launch: recipients [r0, r0 + nblk) of the R
     double mu;
     double kappa;         // storage scale of the resident vector
     double inv_kappa;

@@ -88,7 +88,7 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
     const int nwaves = uniform(blockDim.x >> 6);
     const int wave = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int r = blockIdx.x;
+    const int r = a.r0 + blockIdx.x;
     const int N = a.N, NF = a.NF;
     const int i = recipients[r];
     if (i < 0 || i >= N) {

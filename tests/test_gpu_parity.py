@@ -194,6 +194,27 @@ def test_stale_hip_error_is_not_reported(ls):
     assert np.all(np.isfinite(_np(r["P"])))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_many_recipients_equal_small_decode(ls, prec):
+    """A decode of thousands of recipients (several rounds of workgroups per
+    launch): every recipient's rows must equal those of a small decode bit
+    for bit, and the oracle's."""
+    N, L = 4500, 40
+    H, rho, mu = _random_case(N, L, seed=45)
+    targets = [7, 31]
+    m = ls.Model(H, N, rho, mu)
+    full = ls.decode(m, targets, prec, want=("P",))
+    pick = np.array([0, 1, 2249, 2250, 2251, N - 1], np.int32)
+    part = ls.decode(m, targets, prec, recipients=pick, want=("P",))
+    assert np.array_equal(_np(full["P"])[:, pick, :], _np(part["P"]))
+    assert np.array_equal(_np(full["fwd"].log_scale)[pick], _np(part["fwd"].log_scale))
+    ref = oracle.run_pass(H, N, L, rho, mu, pick, targets, want=("P",))
+    if prec == "fp64":
+        rel_close(_np(part["P"]), ref["P"], F64_RTOL, F64_ATOL_PROB)
+    else:
+        assert np.abs(_np(part["P"]) - ref["P"]).max() <= F32_POST_ATOL
+
+
 def test_recipient_subset_equals_full(ls, c1):
     """Windows of recipients give the same columns (tables are independent
     HMMs, section 3.9)."""
