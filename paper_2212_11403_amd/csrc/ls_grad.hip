@@ -323,6 +323,31 @@ sum_rows_kernel(const double *__restrict__ grow, int32_t R, int32_t rows, double
 hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, double *pac,
                        double *grad_rho, double *grad_mu, hipStream_t st);
 
+// Forward sweep keeping alpha at every variant (segment recompute).
+template <class PT, int NSLOT>
+static hipError_t launch_every_one(const SweepPtrs &p, const SweepArgs &a, int nwaves,
+                                   hipStream_t st) {
+    if (nwaves < 1 || nwaves > max_waves_for(NSLOT, PT::vgpr_per_slot)) return hipErrorInvalidValue;
+    if (a.nblk < 1 || a.r0 < 0 || a.r0 + a.nblk > a.R) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sweep_kernel<PT, NSLOT, 0, true>), dim3(a.nblk), dim3(64 * nwaves), 0, st,
+                       p.Hr, p.rho, p.coef, p.recipients, (typename PT::ST *)p.state,
+                       p.log_scale, p.status, (typename PT::IO *)p.snap, a);
+    return hipGetLastError();
+}
+
+template <class PT>
+static hipError_t launch_every(const SweepPtrs &p, const SweepArgs &a, Shape sh, hipStream_t st) {
+    switch (sh.nslot) {
+#define LS_CASE(n) \
+    case n:        \
+        return launch_every_one<PT, n>(p, a, sh.nwaves, st);
+        LS_MENU_GRAD(LS_CASE)
+#undef LS_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Whole gradient: a forward sweep with checkpoints every `seg` variants (its
 // table also gives log P per recipient), then, segment by segment from the
@@ -335,7 +360,7 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
     const int64_t RN = (int64_t)ga.R * ga.N;
     const size_t es = prec == 0 ? 8 : 4;
     auto sweep = [&](int dir, int l0, int t, const int32_t *tl, int nt, void *state, void *snap,
-                     double *lsc) -> hipError_t {
+                     double *lsc, bool every = false) -> hipError_t {
         SweepPtrs p;
         p.Hr = ga.Hr;
         p.rho = ga.rho;
@@ -368,6 +393,12 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
             a.tgt_l[k] = tl[2 * k];
             a.tgt_out[k] = tl[2 * k + 1];
         }
+        if (every) {
+            a.nt = 0;
+            a.tgt_out[0] = tl[0];
+            return prec == 0 ? launch_every<PrecF64>(p, a, sh, st)
+                             : launch_every<PrecF32>(p, a, sh, st);
+        }
         return prec == 0 ? launch_sweep_f64_fwd(p, a, sh, st) : launch_sweep_f32_fwd(p, a, sh, st);
     };
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ws + Ly.off_status), 0u, ga.R, st);
@@ -399,17 +430,10 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
             e = hipMemcpyAsync(fstate, ws + Ly.off_ckpt + (size_t)k * RN * es, (size_t)RN * es,
                                hipMemcpyDeviceToDevice, st);
             if (e != hipSuccess) return e;
-            int lo = s0;
-            while (lo < s1) {
-                const int hi = std::min(s1, lo + kMaxTargets);
-                for (int q = lo + 1; q <= hi; ++q) {
-                    tl[2 * (q - lo - 1)] = q;
-                    tl[2 * (q - lo - 1) + 1] = q - s0 - 1;
-                }
-                e = sweep(0, lo, hi, tl.data(), hi - lo, fstate, ws + Ly.off_seg, scratch);
-                if (e != hipSuccess) return e;
-                lo = hi;
-            }
+            // alpha^{s0+1..s1} into segment rows 0 .. s1-s0-1
+            const int32_t out0 = 0;
+            e = sweep(0, s0, s1, &out0, 0, fstate, ws + Ly.off_seg, scratch, true);
+            if (e != hipSuccess) return e;
         }
         GradSegArgs sa;
         sa.hr_stride = ga.hr_stride;

@@ -66,9 +66,13 @@ __device__ __forceinline__ SpecSlot special_slot(int q, int NF, int N, int g, bo
     return sp;
 }
 
-template <class PT, int NSLOT, int DIR>
+// EVERY (forward only, kappa = 1): keep alpha at every variant l0+1 .. t, in
+// snap rows tgt_out[0], tgt_out[0]+1, ... (the segment recompute of the
+// gradient); the target list is not used.
+template <class PT, int NSLOT, int DIR, bool EVERY = false>
 __global__ void __launch_bounds__(64 * max_waves_for(NSLOT, PT::vgpr_per_slot))
-__attribute__((amdgpu_waves_per_eu(sweep_waves_per_simd(NSLOT, PT::vgpr_per_slot))))
+__attribute__((amdgpu_waves_per_eu(sweep_waves_per_simd(NSLOT + (EVERY ? 16 : 0),
+                                                         PT::vgpr_per_slot))))
 sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
              const float *__restrict__ coef, const int32_t *__restrict__ recipients, typename PT::ST *__restrict__ state,
              double *__restrict__ log_scale, uint32_t *__restrict__ status,
@@ -329,7 +333,55 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
         // the coefficients and the recipient's own word are read one variant
         // ahead, so their latency overlaps the previous step
         const int lmax = a.L - 1;
-        for (;;) {
+        if constexpr (EVERY) {
+            // per special slot, the byte offset of each lane in a snapshot row;
+            // lanes that hold no donor get an offset past the row, whose store
+            // the buffer range check drops (the entries are exactly 0 anyway)
+            int spec_byte[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                SpecSlot sp = special_slot(nwaves * NR + wave * K + k, NF, N, g, self_full, sw,
+                                           self_bit);
+                spec_byte[k] = (sp.word >= 0 && lane_bit(sp.valid))
+                                   ? (sp.word * 64 + lane) * (int)sizeof(IO)
+                                   : 0x7ffffff0;
+            }
+            const int voff = lane * (int)sizeof(IO);
+            IO *dst = snap + ((int64_t)a.tgt_out[0] * a.R + r) * N;
+            const int64_t dstep = (int64_t)a.R * N;
+            T A_nx, B_nx;
+            coefs_at(l <= lmax ? l : lmax, A_nx, B_nx);
+            uint64_t w_nx = self_word(l <= lmax ? l : lmax);
+            for (; l <= a.t; ++l) {
+                const T A = A_nx, B = B_nx;
+                const uint64_t wb = w_nx;
+                const int ln = l < lmax ? l + 1 : lmax;
+                coefs_at(ln, A_nx, B_nx);
+                w_nx = self_word(ln);
+                const T c = coef_c(A, S);
+                T part = step(l, wb, c, B);
+                S = block_sum<MAXW>(part, red, parity, wave, nwaves);
+                account(S);
+                // alpha^l (exactly 0 on the recipient's lane and on lanes
+                // without a donor), unscaled: kappa = 1 in this mode
+                const rsrc_t rs = make_rsrc(dst, (uint32_t)N * sizeof(IO));
+                const int rb = opaque(reg_base);
+#pragma unroll
+                for (int s = 0; s < NSLOT; ++s) {
+                    if (s < NR) {
+                        int w = rb + s;
+                        if (w >= NF) w -= NF;
+                        buf_store((IO)v[s], rs, voff, w * 64 * (int)sizeof(IO), kStreaming);
+                    } else {
+                        buf_store((IO)v[s], rs, spec_byte[s - NR], 0, kStreaming);
+                    }
+                }
+                // keep the stores of alpha^l ahead of the next update: moved
+                // past it, they would hold a second copy of the column live
+                __builtin_amdgcn_sched_barrier(0);
+                dst += dstep;
+            }
+        } else for (;;) {
             const int lend = kt < a.nt ? a.tgt_l[kt] : a.t;
             T A_nx, B_nx;
             coefs_at(l <= lmax ? l : lmax, A_nx, B_nx);
