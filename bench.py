@@ -33,7 +33,7 @@ VALU_PEAK = 256 * 4 * 32 * 2.4e9
 # FP64 vector peak: 78.6 TFLOP/s, i.e. 39.3e12 FP64 FMA lane-operations/s.
 VALU_PEAK_F64 = 256 * 4 * 16 * 2.4e9
 OPS_PER_CELL = 4                  # emission select, FMA, MUL, ADD per cell per direction
-SWEEP_CHUNK = 4096                # variants per sweep launch (the library splits longer sweeps)
+SWEEP_CHUNK = 2048                # variants per sweep launch (the library splits longer sweeps)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_bwd_fp32_c2_traffic.txt")
 SWEEP_SOURCES = ["ls_sweep.h", "ls_device.h", "ls_internal.h", "ls_sweep_f32_bwd.hip"]
 

@@ -186,10 +186,20 @@ hipError_t launch_sweep(int prec, int dir, const SweepPtrs &p, const SweepArgs &
 // (resumption is exact in FP64 and FP32). Every launch starts all groups at
 // the same variant; within one long launch the groups drift apart, the rows
 // they read at any moment spread beyond the L2 cache and the scalar row loads
-// fall through to the last-level cache (measured: ~14% slower per variant at
-// L = 100,000 than at L = 4,000). FP16-stored tables are not split: their
-// stores round to half.
-constexpr int32_t kSweepChunk = 4096;
+// fall through to the last-level cache. Measured backward sweep at N = 10,000,
+// L = 100,000: one launch 1044 ms; chunks of 8192: 984; 4096: 913; 2048: 882;
+// 1024: 883 ms (row fetches beyond L2: 325 GB at 4096, 62 GB at 1024).
+// FP16-stored tables are not split: their stores round to half.
+constexpr int32_t kSweepChunk = 2048;
+
+// The chunk length (LS_SWEEP_CHUNK overrides it, for tuning).
+int32_t sweep_chunk() {
+    if (const char *env = std::getenv("LS_SWEEP_CHUNK")) {
+        const int v = std::atoi(env);
+        if (v >= 1) return v;
+    }
+    return kSweepChunk;
+}
 
 hipError_t run_chunks(int prec, int dir, const SweepPtrs &p, const SweepArgs &a, Shape sh,
                       hipStream_t st) {
@@ -197,14 +207,15 @@ hipError_t run_chunks(int prec, int dir, const SweepPtrs &p, const SweepArgs &a,
     SweepArgs c = a;
     int32_t l0 = a.l0;
     int next = 0;  // next target, in travel order
+    const int32_t chunk = sweep_chunk();
     for (;;) {
         int32_t tc;
         if (dir == 0) {
             const int32_t from = l0 < 0 ? 0 : l0;
-            tc = std::min(a.t, from + kSweepChunk);
+            tc = std::min(a.t, from + chunk);
         } else {
             const int32_t top = l0 < 0 ? a.L - 1 : l0;
-            tc = std::max(a.t, top - kSweepChunk);
+            tc = std::max(a.t, top - chunk);
         }
         int n = 0;
         while (next + n < a.nt &&
