@@ -65,12 +65,21 @@ __device__ __forceinline__ double read_lane63(double x) {
 }
 
 __device__ __forceinline__ float wave_sum(float x) {
-    x += dpp_f32<0xB1>(x);             // quad_perm [1,0,3,2]
-    x += dpp_f32<0x4E>(x);             // quad_perm [2,3,0,1]
-    x += dpp_f32<0x124>(x);            // row_ror:4
-    x += dpp_f32<0x128>(x);            // row_ror:8
-    x += dpp_f32<0x142, 0xA, 0xF, false>(x);  // row_bcast:15 into rows 1, 3
-    x += dpp_f32<0x143, 0xC, 0xF, false>(x);  // row_bcast:31 into rows 2, 3
+    x += dpp_f32<0xB1>(x);   // quad_perm [1,0,3,2]
+    x += dpp_f32<0x4E>(x);   // quad_perm [2,3,0,1]
+    x += dpp_f32<0x124>(x);  // row_ror:4
+    x += dpp_f32<0x128>(x);  // row_ror:8
+    // Row broadcasts as single DPP adds: rows outside row_mask are not
+    // written and keep x (the compiler expresses them as a DPP move into a
+    // zeroed register plus an add). s_nop 1 gives the two wait states a DPP
+    // read of a just-written VGPR needs.
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "s_nop 1"
+        : "+v"(x));
     return read_lane63(x);
 }
 
@@ -79,8 +88,8 @@ __device__ __forceinline__ double wave_sum(double x) {
     x += dpp_f64<0x4E>(x);
     x += dpp_f64<0x124>(x);
     x += dpp_f64<0x128>(x);
-    x += dpp_f64<0x142, 0xA, 0xF, false>(x);
-    x += dpp_f64<0x143, 0xC, 0xF, false>(x);
+    x += dpp_f64<0x142, 0xA, 0xF, false>(x);  // row_bcast:15 into rows 1, 3
+    x += dpp_f64<0x143, 0xC, 0xF, false>(x);  // row_bcast:31 into rows 2, 3
     return read_lane63(x);
 }
 
@@ -240,7 +249,7 @@ __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirs
 // are therefore kept in VGPRs.
 __device__ __forceinline__ float in_vgpr(float x) {
     float y;
-    asm volatile("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
+    asm volatile("v_mov_b32 %0, %1" : "=v"(y) : "s"(x));
     return y;
 }
 __device__ __forceinline__ double in_vgpr(double x) {

@@ -146,6 +146,15 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
         ta = rb ? mu : omu;
         tb = rb ? omu : mu;
     };
+    // Lane partial sums of the column: even slots into acc0, odd into acc1,
+    // starting from slots 0 and 1 (the entries are never -0, so this equals
+    // adding them to zero).
+    auto accumulate = [&](int s, T x, T &acc0, T &acc1) __attribute__((always_inline)) {
+        if (s == 0) acc0 = x;
+        else if (s == 1) acc1 = x;
+        else if (s & 1) acc1 += x;
+        else acc0 += x;
+    };
     // Row words of slot s at variant row `row`.
     auto mask_of = [&](const uint64_t *row, int s) __attribute__((always_inline)) -> uint64_t {
         return (s < NR) ? row[reg_base + s] : row[spec_off[s - NR]];
@@ -156,15 +165,14 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
         T ta, tb;
         thetas(sw_bits, ta, tb);
         const T b = in_vgpr(b_s);
-        T acc0 = 0, acc1 = 0;
+        T acc0, acc1 = (T)0;
 #pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
             const T th = lane_bit(mask_of(row, s)) ? tb : ta;
             const T bb = (s < NR) ? (s == 0 ? b * keep0 : b) : b * spec_keep[s - NR];
             const T nv = th * fma(c, (T)v[s], bb);
             v[s] = nv;
-            if (s & 1) acc1 += nv;
-            else acc0 += nv;
+            accumulate(s, nv, acc0, acc1);
         }
         return acc0 + acc1;
     };
@@ -182,14 +190,13 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
         const uint64_t *row = Hr + (int64_t)l * a.hr_stride;
         T ta, tb;
         thetas(row[self_off], ta, tb);
-        T acc0 = 0, acc1 = 0;
+        T acc0, acc1 = (T)0;
 #pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
             const T th = lane_bit(mask_of(row, s)) ? tb : ta;
             const T nv = th * v[s];
             v[s] = nv;
-            if (s & 1) acc1 += nv;
-            else acc0 += nv;
+            accumulate(s, nv, acc0, acc1);
         }
         return acc0 + acc1;
     };
@@ -322,12 +329,9 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
             l = 0;
         } else {
             l = a.l0 + 1;
-            T acc0 = 0, acc1 = 0;  // same order as in step()
+            T acc0, acc1 = (T)0;  // same order as in step()
 #pragma unroll
-            for (int s = 0; s < NSLOT; ++s) {
-                if (s & 1) acc1 += (T)v[s];
-                else acc0 += (T)v[s];
-            }
+            for (int s = 0; s < NSLOT; ++s) accumulate(s, v[s], acc0, acc1);
             S = block_sum<MAXW>(acc0 + acc1, red, parity, wave, nwaves);
         }
         // the coefficients and the recipient's own word are read one variant
