@@ -9,6 +9,9 @@
                          mosaic, 20 targets): FP32 and FP16-stored posteriors
                          and log-likelihoods vs the FP64 oracle on seeded
                          recipients, and the decode time of all recipients
+    python study.py c2   FP32 against FP64 on the benchmark workload (N = 10,000,
+                         L = 100,000, 100 targets) over all recipients and
+                         targets: posterior and distance errors
     python study.py c5   the share of one GPU of the large workload
                          (N = 100,000, L = 10,000, 5 targets): recipients
                          [0, 12,500) against all 100,000 donors, FP32 decode
@@ -237,17 +240,74 @@ def study_c5(args):
     print(json.dumps(out), flush=True)
 
 
+def study_c2(args):
+    import torch
+
+    import paper_2212_11403_amd as ls
+    from lsinputs import make_inputs
+
+    x = make_inputs("c2")
+    N, L, targets = x["N"], x["L"], x["targets"]
+    model = ls.Model(x["H"], N, x["rho"], x["mu"])
+    eps = 2.0 ** -52
+    floor_half = -0.5 * np.log(eps)
+    worst_p = worst_d = 0.0
+    floor_diff = 0
+    considered = 0
+    win = args.targets_per_window
+    t0 = time.perf_counter()
+    for lo in range(0, len(targets), win):
+        tw = targets[lo:lo + win]
+        r64 = ls.decode(model, tw, "fp64", want=("P",))
+        P64 = r64["P"]
+        del r64
+        r32 = ls.decode(model, tw, "fp32", want=("P",))
+        P32 = r32["P"]
+        del r32
+        for k in range(len(tw)):
+            a = P64[k]
+            b = P32[k].double()
+            worst_p = max(worst_p, float((a - b).abs().max().item()))
+            # distances d_ji = -(log max(p_ji, eps) + log max(p_ij, eps)) / 2
+            ea = -0.5 * torch.log(torch.clamp(a, min=eps))
+            eb = -0.5 * torch.log(torch.clamp(b, min=eps))
+            da = ea + ea.T
+            db = eb + eb.T
+            keep = (a >= 1e-4) & (a.T >= 1e-4)
+            if bool(keep.any()):
+                worst_d = max(worst_d, float((da - db).abs()[keep].max().item()))
+            considered += int(keep.sum().item())
+            fa = (a < eps)
+            fb = (b < eps)
+            floor_diff += int((fa != fb).sum().item())
+            del a, b, ea, eb, da, db, keep, fa, fb
+        del P64, P32
+        torch.cuda.empty_cache()
+        log(f"targets {lo}..{lo + len(tw) - 1}: worst posterior error so far {worst_p:.3e}")
+    out = {"study": "c2 fp32 vs fp64, all recipients", "N": N, "L": L, "targets": len(targets),
+           "max_abs_posterior_err": worst_p,
+           "max_abs_distance_err_where_both_p_ge_1e-4": worst_d,
+           "distance_entries_compared": considered,
+           "eps_floor_decisions_differing": floor_diff,
+           "half_distance_floor": floor_half,
+           "seconds": time.perf_counter() - t0}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c3", "c4", "c5"])
+    ap.add_argument("which", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--recipients", type=int, default=None,
                     help="seeded recipients checked against the oracle")
     ap.add_argument("--fd", type=int, default=16, help="finite-difference components (c4)")
     ap.add_argument("--window", type=int, default=12_500, help="recipients per decode (c3)")
+    ap.add_argument("--targets-per-window", type=int, default=20, help="targets per decode (c2)")
     args = ap.parse_args()
     import paper_2212_11403_amd as ls
     ls.load()
-    if args.which == "c4":
+    if args.which == "c2":
+        study_c2(args)
+    elif args.which == "c4":
         args.recipients = args.recipients or 64
         study_c4(args)
     elif args.which == "c3":
