@@ -215,6 +215,28 @@ def test_many_recipients_equal_small_decode(ls, prec):
         assert np.abs(_np(part["P"]) - ref["P"]).max() <= F32_POST_ATOL
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_sweep_chunk_length_does_not_change_results(ls, prec, monkeypatch):
+    """Sweeps resume from the table at every chunk boundary: any chunk length
+    gives the same vectors bit for bit (the log scales are summed per chunk,
+    so they agree to rounding)."""
+    N, L = 300, 500
+    H, rho, mu = _random_case(N, L, seed=77)
+    targets = [3, 160, 161, 499]
+    m = ls.Model(H, N, rho, mu)
+    res = {}
+    for chunk in ("7", "64", "100000"):
+        monkeypatch.setenv("LS_SWEEP_CHUNK", chunk)
+        r = ls.decode(m, targets, prec, want=("P",))
+        res[chunk] = (_np(r["P"]), _np(r["bsnap"]), _np(r["fwd"].log_scale),
+                      _np(r["bck"].log_scale))
+    for chunk in ("7", "64"):
+        assert np.array_equal(res[chunk][0], res["100000"][0])
+        assert np.array_equal(res[chunk][1], res["100000"][1])
+        for q in (2, 3):
+            assert np.allclose(res[chunk][q], res["100000"][q], rtol=1e-13, atol=1e-12)
+
+
 def test_recipient_subset_equals_full(ls, c1):
     """Windows of recipients give the same columns (tables are independent
     HMMs, section 3.9)."""
