@@ -146,17 +146,19 @@ void fill_scalars(SweepArgs &a, const ls_model *m, int prec, int dir) {
     a.N = m->N;
     a.L = m->L;
     a.NF = m->N / 64;
-    a.mu = m->mu;
+    const lsk::Emissions em = lsk::sweep_emissions(m->mu, prec != LS_FP64);
+    a.th_match = em.match;
+    a.th_mis = em.mis;
     a.kappa = kappa;
     a.inv_kappa = 1.0 / kappa;
     if (dir == 0) {
         a.cnum = kappa;
         a.bmul = kappa / n1;
-        a.log_off = -std::log(kappa);
+        a.log_off = em.log_unit - std::log(kappa);
     } else {
         a.cnum = kappa * n1;
         a.bmul = kappa;
-        a.log_off = -std::log(n1 * kappa);
+        a.log_off = em.log_unit - std::log(n1 * kappa);
     }
 }
 

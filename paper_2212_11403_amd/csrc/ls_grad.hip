@@ -95,7 +95,7 @@ hipError_t launch_loglik_sum(const double *ll, int32_t R, double *loglik, double
 // Sy = sum_j y^{l+1}_j (all reductions over the donor column),
 //   d log P / d rho_l = (pi Sa Sy - d) / ((1 - rho_l) d + rho_l pi Sa Sy)
 // (the exact score of the transition; homogeneous in alpha and y, so any
-// scaling of the stored vectors cancels), and, with beta^l = c y^{l+1} + b,
+// scaling of the stored vectors cancels, the FP32 emission unit included), and, with beta^l = c y^{l+1} + b,
 //   M_l = sum_{j mismatching at l} alpha^l_j beta^l_j / sum_j alpha^l_j beta^l_j
 //   d log P / d mu += M_l / mu - (1 - M_l) / (1 - mu).
 // Per-variant rho terms go to grow[l][r]; the mu term accumulates in gmu[r].
@@ -104,6 +104,7 @@ struct GradSegArgs {
     int32_t N, L, NF, R;
     int32_t s0, s1;
     double mu;
+    double th_match, th_mis;  // the sweep's emission pair (sweep_emissions)
 };
 
 template <class PT, int NSLOT>
@@ -147,7 +148,7 @@ grad_seg_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
         spec_keep[k] = lane_bit(sp.bmask) ? (T)1 : (T)0;
         spec_voff[k] = (sp.word >= 0 && lane_bit(sp.valid)) ? sp.word * 64 + lane : 0;
     }
-    const T mu = (T)a.mu, omu = (T)((1.0 - 2.0 * a.mu) + a.mu);
+    const T th_m = (T)a.th_match, th_x = (T)a.th_mis;
     const double pi = 1.0 / (double)(N - 1);
     const int voff = lane * (int)sizeof(T);
     auto word_of = [&](int s) __attribute__((always_inline)) -> int {
@@ -169,7 +170,7 @@ grad_seg_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
         const uint64_t *row = Hr + (int64_t)ll * a.hr_stride;
         const bool rb = (row[self_off] & self_bit) != 0;
         const uint64_t flip = rb ? ~0ull : 0ull;
-        const T ta = rb ? mu : omu, tb = rb ? omu : mu;
+        const T ta = rb ? th_x : th_m, tb = rb ? th_m : th_x;
         const rsrc_t rs = make_rsrc(alpha_row(ll), (uint32_t)N * sizeof(T));
         T d = 0, sa = 0, mn = 0, sy = 0;
 #pragma unroll
@@ -359,6 +360,7 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
     char *ws = ga.ws;
     const int64_t RN = (int64_t)ga.R * ga.N;
     const size_t es = prec == 0 ? 8 : 4;
+    const Emissions em = sweep_emissions(ga.mu, prec != 0);
     auto sweep = [&](int dir, int l0, int t, const int32_t *tl, int nt, void *state, void *snap,
                      double *lsc, bool every = false) -> hipError_t {
         SweepPtrs p;
@@ -383,12 +385,13 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
         a.nt = nt;
         a.r0 = 0;
         a.nblk = ga.R;
-        a.mu = ga.mu;
+        a.th_match = em.match;
+        a.th_mis = em.mis;
         a.kappa = 1.0;
         a.inv_kappa = 1.0;
         a.cnum = 1.0;
         a.bmul = 1.0 / (double)(ga.N - 1);
-        a.log_off = 0.0;
+        a.log_off = em.log_unit;
         for (int k = 0; k < nt; ++k) {
             a.tgt_l[k] = tl[2 * k];
             a.tgt_out[k] = tl[2 * k + 1];
@@ -444,6 +447,8 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
         sa.s0 = s0;
         sa.s1 = s1;
         sa.mu = ga.mu;
+        sa.th_match = em.match;
+        sa.th_mis = em.mis;
         e = prec == 0 ? dispatch_grad_seg<PrecF64>(ga, sa, sh, st)
                       : dispatch_grad_seg<PrecF32>(ga, sa, sh, st);
         if (e != hipSuccess) return e;

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <cmath>
+
 namespace lsk {
 
 constexpr int kWave = 64;
@@ -37,15 +39,34 @@ struct SweepArgs {
     int32_t t;            // variant to stop at
     int32_t nt;           // number of targets visited, in travel order
     int32_t r0, nblk;     // this launch: recipients [r0, r0 + nblk) of the R
-    double mu;
+    double th_match;      // emission where the donor carries the recipient's allele
+    double th_mis;        // and where it does not (see sweep_emissions)
     double kappa;         // storage scale of the resident vector
     double inv_kappa;
     double cnum;          // forward: kappa; backward: kappa * (N-1)
     double bmul;          // forward: kappa / (N-1); backward: kappa
-    double log_off;       // per-step log offset: fwd -log(kappa), bwd -log((N-1) kappa)
+    double log_off;       // per-step log offset: fwd -log(kappa), bwd -log((N-1) kappa),
+                          // plus the emission unit's log (see sweep_emissions)
     int32_t tgt_l[kMaxTargets];    // variant of each visited target, travel order
     int32_t tgt_out[kMaxTargets];  // its index k in the [T] output arrays
 };
+
+// The emission pair a sweep multiplies by, from the form (1-H)(1-2mu)+mu of
+// appendix A.3 evaluated in FP64. The FP64 sweep uses the emissions as they
+// are. Sweeps in FP32 arithmetic use both divided by the match value 1-mu:
+// the match factor is then exactly 1 and adds no rounding to most cells,
+// where the rounded 1-mu would bias every step's sum the same way (a
+// log-likelihood error growing with L). Dividing every step's emissions by
+// one constant only rescales the vectors, so its log (`log_unit`) is added
+// to the per-step log offset in FP64.
+struct Emissions {
+    double match, mis, log_unit;
+};
+inline Emissions sweep_emissions(double mu, bool fp32_arith) {
+    const double omu = (1.0 - 2.0 * mu) + mu;
+    if (!fp32_arith) return Emissions{omu, mu, 0.0};
+    return Emissions{1.0, mu / omu, std::log(omu)};
+}
 
 // Kernel shape: 64-donor register slots per wave, waves per recipient.
 struct Shape {

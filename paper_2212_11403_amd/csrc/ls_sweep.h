@@ -6,7 +6,8 @@
 // Both directions run the same update on a resident vector v:
 //   v <- theta^l (.) (c v + b),  c = num / sum(v_prev),  b = rho-term,
 // where (.) is the elementwise product and theta^l_j is 1-mu on a match of
-// donor j with the recipient at variant l and mu on a mismatch.
+// donor j with the recipient at variant l and mu on a mismatch (in FP32
+// arithmetic: 1 and mu/(1-mu), with log(1-mu) per step in the log offset).
 //   forward:  v = kappa alpha^l,          c = (1-rho_{l-1}) kappa / S,
 //             b = kappa rho_{l-1} / (N-1); log F^l = log F^{l-1} + log(S_l / kappa)
 //   backward: v = kappa beta^l theta^l,   c = (1-rho_l) kappa (N-1) / S,
@@ -120,9 +121,9 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
         spec_keep[k] = lane_bit(sp.bmask) ? (T)1 : (T)0;
     }
     const T keep0 = lane_bit(m0) ? (T)1 : (T)0;
-    // emissions in the form of appendix A.3, (1-H)(1-2mu)+mu, evaluated in
-    // FP64 and rounded once to the sweep precision
-    const T mu = (T)a.mu, omu = (T)((1.0 - 2.0 * a.mu) + a.mu);
+    // the emission pair (match, mismatch), formed in FP64 by the host and
+    // rounded once to the sweep precision
+    const T th_m = (T)a.th_match, th_x = (T)a.th_mis;
 
     // resident vector in the arithmetic precision; the table state (ST) is
     // converted only when it is loaded or stored
@@ -143,8 +144,8 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
     // the donor bit is 0, where it is 1
     auto thetas = [&](uint64_t sw_bits, T &ta, T &tb) __attribute__((always_inline)) {
         const bool rb = (sw_bits & self_bit) != 0;
-        ta = rb ? mu : omu;
-        tb = rb ? omu : mu;
+        ta = rb ? th_x : th_m;
+        tb = rb ? th_m : th_x;
     };
     // Lane partial sums of the column: even slots into acc0, odd into acc1,
     // starting from slots 0 and 1 (the entries are never -0, so this equals
@@ -294,12 +295,21 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
             B = rr * a.bmul;
         }
     };
-    // c = A / S in the sweep precision: FP64 divides (correctly rounded),
-    // FP32 multiplies by the hardware reciprocal (within 1 ulp), which is
-    // below the rounding of the FP32 update itself
+    // c = A / S in the sweep precision. FP64 divides (correctly rounded).
+    // FP32 refines the hardware reciprocal (about 1 ulp, and its error has a
+    // consistent sign, which the log scale would sum over every step) by one
+    // Newton step and corrects the quotient once, which gives A / S rounded
+    // to nearest in all but rare ties; a zero or non-finite S gives a NaN or
+    // infinite c, as the division would.
     auto coef_c = [&](T A, T sum) __attribute__((always_inline)) -> T {
-        if constexpr (sizeof(T) == 4) return A * __builtin_amdgcn_rcpf(sum);
-        else return A / sum;
+        if constexpr (sizeof(T) == 4) {
+            const float r0 = __builtin_amdgcn_rcpf(sum);
+            const float r1 = fmaf(fmaf(-sum, r0, 1.0f), r0, r0);
+            const float q = A * r1;
+            return fmaf(fmaf(-sum, q, A), r1, q);
+        } else {
+            return A / sum;
+        }
     };
     auto account = [&](T sum) __attribute__((always_inline)) {
         int e;
@@ -335,7 +345,8 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
             S = block_sum<MAXW>(acc0 + acc1, red, parity, wave, nwaves);
         }
         // the coefficients and the recipient's own word are read one variant
-        // ahead, so their latency overlaps the previous step
+        // ahead, so their latency overlaps the previous step, and c of the
+        // next variant is formed as soon as the column sum is known
         const int lmax = a.L - 1;
         if constexpr (EVERY) {
             // per special slot, the byte offset of each lane in a snapshot row;
@@ -356,15 +367,16 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
             T A_nx, B_nx;
             coefs_at(l <= lmax ? l : lmax, A_nx, B_nx);
             uint64_t w_nx = self_word(l <= lmax ? l : lmax);
+            T c_nx = coef_c(A_nx, S);
             for (; l <= a.t; ++l) {
-                const T A = A_nx, B = B_nx;
+                const T c = c_nx, B = B_nx;
                 const uint64_t wb = w_nx;
                 const int ln = l < lmax ? l + 1 : lmax;
                 coefs_at(ln, A_nx, B_nx);
                 w_nx = self_word(ln);
-                const T c = coef_c(A, S);
                 T part = step(l, wb, c, B);
                 S = block_sum<MAXW>(part, red, parity, wave, nwaves);
+                c_nx = coef_c(A_nx, S);
                 account(S);
                 // alpha^l (exactly 0 on the recipient's lane and on lanes
                 // without a donor), unscaled: kappa = 1 in this mode
@@ -390,16 +402,18 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
             T A_nx, B_nx;
             coefs_at(l <= lmax ? l : lmax, A_nx, B_nx);
             uint64_t w_nx = self_word(l <= lmax ? l : lmax);
+            T c_nx = coef_c(A_nx, S);
             for (; l <= lend; ++l) {
-                const T A = A_nx, B = B_nx;
+                const T c = c_nx, b = B_nx;
                 const uint64_t wb = w_nx;
                 const int ln = l < lmax ? l + 1 : lmax;
                 coefs_at(ln, A_nx, B_nx);
                 w_nx = self_word(ln);
-                const T c = coef_c(A, S);
-                const T b = B;
                 T part = step(l, wb, c, b);
                 S = block_sum<MAXW>(part, red, parity, wave, nwaves);
+                // the next variant's c (its A was read at the top), next to
+                // the log-scale update so that the two chains overlap
+                c_nx = coef_c(A_nx, S);
                 account(S);
             }
             if (kt < a.nt) snapshot();

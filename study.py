@@ -16,6 +16,14 @@
                          (N = 100,000, L = 10,000, 5 targets): recipients
                          [0, 12,500) against all 100,000 donors, FP32 decode
                          time, E-write bandwidth, posterior error vs the oracle
+    python study.py emu  (CPU only) numpy emulation of the FP32 forward sweep
+                         against the same recursion in FP64, with the column
+                         sum taken in the kernel's order, with Kahan lane sums
+                         and an FP64 tree, or exactly rounded; the emissions
+                         plain or divided by 1-mu; c = A/S rounded to nearest
+                         or through a reciprocal with a one-sided 1-ulp error.
+                         Reports the log-likelihood error and the error of the
+                         renormalised vectors for each variant.
 
 Inputs are the seeded synthetic workloads of `lsinputs`; the oracle runs on
 the host's cores.
@@ -294,15 +302,163 @@ def study_c2(args):
     print(json.dumps(out), flush=True)
 
 
+class _Fp32Forward:
+    """FP32 forward recursion of the copying model (eq. fwd0, fwd1) over R
+    recipients, vectorised over donors, with the rounding of each operation
+    made explicit so that the variants of the study differ in one place.
+
+    The donor column of a recipient is laid out as the sweep kernel holds it:
+    `nslot` slots per lane, 64 lanes per wave, `nwaves` waves (zero padded).
+    """
+
+    def __init__(self, h, rho, mu, rec, nslot, nwaves):
+        self.h, self.rho, self.mu, self.rec = h, rho, mu, rec
+        self.nslot, self.nwaves = nslot, nwaves
+        L, N = h.shape
+        assert 64 * nslot * nwaves >= N
+
+    def colsum(self, v, how):
+        f32 = np.float32
+        if how == "exact":
+            return v.astype(np.float64).sum(axis=1).astype(f32)
+        R, N = v.shape
+        P = 64 * self.nslot * self.nwaves
+        x = np.zeros((R, P), f32)
+        x[:, :N] = v
+        x = x.reshape(R, self.nwaves, self.nslot, 64)
+        if how == "kahan":
+            acc = x[:, :, 0].copy()
+            comp = np.zeros_like(acc)
+            for s in range(1, self.nslot):
+                y = (x[:, :, s] - comp).astype(f32)
+                t = (acc + y).astype(f32)
+                comp = ((t - acc).astype(f32) - y).astype(f32)
+                acc = t
+            lanes = acc.astype(np.float64) - comp.astype(np.float64)
+            return lanes.sum(axis=(1, 2)).astype(f32)
+        # kernel order: even and odd slots in two chains per lane, the chains
+        # added, a pairwise tree over the 64 lanes, then the waves in order
+        a0, a1 = x[:, :, 0].copy(), x[:, :, 1].copy()
+        for s in range(2, self.nslot):
+            if s & 1:
+                a1 = (a1 + x[:, :, s]).astype(f32)
+            else:
+                a0 = (a0 + x[:, :, s]).astype(f32)
+        t = (a0 + a1).astype(f32)
+        while t.shape[-1] > 1:
+            t = (t[..., 0::2] + t[..., 1::2]).astype(f32)
+        t = t[..., 0]
+        acc = t[:, 0].copy()
+        for w in range(1, self.nwaves):
+            acc = (acc + t[:, w]).astype(f32)
+        return acc
+
+    def run(self, prec, summation="kernel", emission="plain", recip="nearest", every=500):
+        h, rho, mu, rec = self.h, self.rho, self.mu, self.rec
+        L, N = h.shape
+        R = len(rec)
+        f64 = prec == "fp64"
+        ft = np.float64 if f64 else np.float32
+        keep = np.ones((R, N), ft)
+        keep[np.arange(R), rec] = 0
+        omu = (1.0 - 2.0 * mu) + mu
+        if emission == "unit" and not f64:
+            th_m, th_x, log_unit = np.float32(1.0), np.float32(mu / omu), np.log(omu)
+        else:
+            th_m, th_x, log_unit = ft(omu), ft(mu), 0.0
+        ll = np.zeros(R)
+        snaps = []
+        v = None
+        for l in range(L):
+            same = h[l][None, :] == h[l][rec][:, None]
+            th = np.where(same, th_m, th_x).astype(ft)
+            if l == 0:
+                v = (th * (keep * ft(1.0 / (N - 1)))).astype(ft)
+            else:
+                if f64:
+                    S = v.sum(axis=1)
+                    c = (1.0 - rho[l - 1]) / S
+                    pre = c[:, None] * v + (rho[l - 1] / (N - 1)) * keep
+                else:
+                    S = self.colsum(v, summation)
+                    A = np.float32(1.0 - rho[l - 1])
+                    if recip == "nearest":
+                        c = (A / S).astype(np.float32)
+                    else:
+                        exact = 1.0 / S.astype(np.float64)
+                        r = exact.astype(np.float32)
+                        toward = np.float32(0.0) if recip == "low" else np.float32(np.inf)
+                        off = (r.astype(np.float64) > exact) if recip == "low" else \
+                              (r.astype(np.float64) < exact)
+                        r = np.where(off, np.nextafter(r, toward), r)
+                        c = (A * r).astype(np.float32)
+                    b = np.float32(rho[l - 1] / (N - 1))
+                    # c v + b with one rounding (a fused multiply-add)
+                    pre = (c[:, None].astype(np.float64) * v + float(b) * keep).astype(np.float32)
+                ll += np.log(np.asarray(S, np.float64)) + log_unit
+                v = (th * pre).astype(ft)
+            if l % every == every - 1:
+                w = v.astype(np.float64)
+                snaps.append(w / w.sum(axis=1, keepdims=True))
+        ll += np.log(v.astype(np.float64).sum(axis=1)) + log_unit
+        return ll, snaps
+
+
+def study_emu(args):
+    from lsinputs.mosaic import MosaicSpec, mosaic_haplotypes, rho_from_spacings, spacings
+
+    N, L, R = args.emu_n, args.emu_l, args.recipients
+    spec = MosaicSpec(n_haps=N, n_variants=L, n_founders=200, switch=1e-3, flip=1e-4, seed=5)
+    _, h = mosaic_haplotypes(spec, unpacked=True)
+    rho = rho_from_spacings(spacings(L - 1, 1e-3, 7))
+    mu = 1e-4
+    rec = np.arange(R) * (N // R)
+    nslot = 40
+    nwaves = -(-N // (64 * nslot))
+    em = _Fp32Forward(np.asarray(h, np.uint8), rho, mu, rec, nslot, nwaves)
+    t0 = time.perf_counter()
+    ll64, ref = em.run("fp64")
+    variants = [
+        ("kernel", "plain", "low"), ("kernel", "plain", "high"),
+        ("kernel", "plain", "nearest"), ("kahan", "plain", "nearest"),
+        ("exact", "plain", "nearest"), ("kernel", "unit", "nearest"),
+        ("exact", "unit", "nearest"),
+    ]
+    rows = []
+    for summation, emission, recip in variants:
+        ll, snaps = em.run("fp32", summation, emission, recip)
+        d = np.concatenate([np.abs(a - b).ravel() for a, b in zip(snaps, ref)])
+        w = np.concatenate([b.ravel() for b in ref])
+        big = w >= 1e-3
+        lle = np.abs(ll - ll64) / np.abs(ll64)
+        rows.append({"sum": summation, "emission": emission, "reciprocal": recip,
+                     "loglik_rel_err_max": float(lle.max()),
+                     "loglik_rel_err_mean": float(lle.mean()),
+                     "vector_max_abs_err": float(d.max()),
+                     "vector_rel_rms_err_where_ge_1e-3": float(np.sqrt(np.mean((d[big] / w[big]) ** 2)))})
+        log(f"{summation}/{emission}/{recip}: loglik {lle.mean():.2e} (mean rel), "
+            f"vector rel-rms {rows[-1]['vector_rel_rms_err_where_ge_1e-3']:.2e}")
+    out = {"study": "FP32 forward sweep emulation", "N": N, "L": L, "recipients": R,
+           "layout": f"{nslot} slots x 64 lanes x {nwaves} waves", "mean_loglik": float(ll64.mean()),
+           "variants": rows, "seconds": time.perf_counter() - t0}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("which", choices=["c2", "c3", "c4", "c5", "emu"])
     ap.add_argument("--recipients", type=int, default=None,
                     help="seeded recipients checked against the oracle")
     ap.add_argument("--fd", type=int, default=16, help="finite-difference components (c4)")
     ap.add_argument("--window", type=int, default=12_500, help="recipients per decode (c3)")
     ap.add_argument("--targets-per-window", type=int, default=20, help="targets per decode (c2)")
+    ap.add_argument("--emu-n", type=int, default=5000, help="haplotypes (emu)")
+    ap.add_argument("--emu-l", type=int, default=10_000, help="variants (emu)")
     args = ap.parse_args()
+    if args.which == "emu":
+        args.recipients = args.recipients or 32
+        study_emu(args)
+        return
     import paper_2212_11403_amd as ls
     ls.load()
     if args.which == "c2":

@@ -9,7 +9,7 @@ import pytest
 import oracle
 from lsinputs import make_inputs, pack_haplotypes, rho_from_spacings, seeded_recipients
 
-from _gpu import need_gpu
+from _gpu import F32_LOGLIK_RTOL, need_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -62,11 +62,15 @@ def test_gradient_vs_oracle(ls, N, L, prec):
         assert np.abs(g_rho - gr).max() <= 1e-10 * scale
         assert abs(g_mu - gm) <= 1e-10 * max(abs(gm), 1.0)
     else:
-        assert abs(pac - ll) <= 1e-5 * abs(ll)
+        assert abs(pac - ll) <= F32_LOGLIK_RTOL * abs(ll)
+        rel_r = np.abs(g_rho - gr).max() / max(np.abs(gr).max(), 1.0)
+        print(f"N={N} L={L} fp32: PAC rel err {abs(pac - ll) / abs(ll):.3e}, "
+              f"rho grad err {rel_r:.3e}, mu grad err {abs(g_mu - gm) / max(abs(gm), 1.0):.3e}")
         # norm-wise, with a floor: for N = 2 the exact rho gradient is 0
+        # (observed at most 7e-8 and 9e-8)
         scale = max(np.abs(gr).max(), 1.0)
-        assert np.abs(g_rho - gr).max() <= 1e-4 * scale
-        assert abs(g_mu - gm) <= 1e-4 * max(abs(gm), 1.0)
+        assert np.abs(g_rho - gr).max() <= 1e-6 * scale
+        assert abs(g_mu - gm) <= 1e-6 * max(abs(gm), 1.0)
 
 
 def test_gradient_recipient_subset(ls):
@@ -130,9 +134,10 @@ def test_differentiation_workload_sampled(ls):
     ll, gr, gm = _oracle_sum(x["H"], N, L, rho, mu, rec)
     gr32 = g32["grad_rho"].cpu().numpy()
     rel = np.abs(gr32 - gr).max() / np.abs(gr).max()
-    print(f"c4 fp32 adjoint vs oracle: norm-wise rel err {rel:.3e}; "
-          f"mu: {abs(g32['grad_mu'].item() - gm) / abs(gm):.3e}")
-    assert rel <= 1e-4
+    rel_mu = abs(g32["grad_mu"].item() - gm) / abs(gm)
+    print(f"c4 fp32 adjoint vs oracle: norm-wise rel err {rel:.3e}; mu: {rel_mu:.3e}")
+    assert rel <= 1e-6       # observed 4e-8
+    assert rel_mu <= 5e-6    # observed 2e-7
     rng = np.random.default_rng(7)
     cand = np.nonzero(rho >= 1e-4)[0]
     picks = rng.choice(cand, 6, replace=False)

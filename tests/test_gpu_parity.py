@@ -8,8 +8,8 @@ import pytest
 import oracle
 from lsinputs import make_inputs, pack_haplotypes, rho_from_spacings
 
-from _gpu import (F32_POST_ATOL, F64_ATOL_LOG, F64_ATOL_PROB, F64_RTOL, forced_shape, need_gpu,
-                  rel_close)
+from _gpu import (F32_LOGLIK_RTOL, F32_POST_ATOL, F64_ATOL_LOG, F64_ATOL_PROB, F64_RTOL,
+                  forced_shape, need_gpu, rel_close)
 
 pytestmark = pytest.mark.gpu
 
@@ -95,13 +95,12 @@ def test_c1_reduced_precision(ls, c1, c1_ref, prec):
     m = ls.Model(x["H"], x["N"], x["rho"], x["mu"])
     r = ls.decode(m, x["targets"], prec, want=("P", "E"))
     err = np.abs(_np(r["P"]) - ref["P"]).max()
-    llerr = np.abs(_np(r["fwd"].log_scale) - ref["llf"]).max()
-    print(f"{prec}: max abs posterior error {err:.3e}, max abs loglik error {llerr:.3e}")
-    if prec == "fp32":
-        assert err <= F32_POST_ATOL
-        assert llerr <= 1e-3
-    else:
-        assert err <= 5e-2
+    llerr = np.max(np.abs(_np(r["fwd"].log_scale) - ref["llf"]) / np.abs(ref["llf"]))
+    print(f"{prec}: max abs posterior error {err:.3e}, max rel loglik error {llerr:.3e}")
+    # FP16 storage only touches tables kept between calls; decode sweeps in
+    # FP32 registers throughout, so both precisions meet the FP32 bounds
+    assert err <= F32_POST_ATOL
+    assert llerr <= F32_LOGLIK_RTOL
 
 
 # ---------------------------------------------------------------------------
@@ -175,7 +174,7 @@ def test_forced_wide_shapes(ls, prec, N, ns, nw):
         rel_close(_np(r["fwd"].log_scale), ref["llf"], F64_RTOL, F64_ATOL_LOG)
     else:
         assert np.abs(_np(r["P"]) - ref["P"]).max() <= F32_POST_ATOL
-        assert np.max(np.abs(_np(r["fwd"].log_scale) - ref["llf"]) / np.abs(ref["llf"])) <= 1e-5
+        assert np.max(np.abs(_np(r["fwd"].log_scale) - ref["llf"]) / np.abs(ref["llf"])) <= F32_LOGLIK_RTOL
 
 
 def test_stale_hip_error_is_not_reported(ls):
