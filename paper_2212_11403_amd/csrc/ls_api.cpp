@@ -96,9 +96,9 @@ bool shape_fits(int32_t N, int prec, int nslot, int nwaves) {
 // hide the per-step load, reduction and barrier latency, and by the uneven
 // spread of the group's waves over the four SIMDs of a compute unit (every
 // step ends in a barrier, so the busiest SIMD sets the pace).
-double shape_cost(int32_t N, int prec, int ns, int nw) {
+double shape_cost(int32_t N, int prec, int ns, int nw, int wps = 0) {
     const bool f64 = prec == LS_FP64;
-    const int wps = lsk::sweep_waves_per_simd(ns, vgpr_per_slot(prec));
+    if (wps <= 0) wps = lsk::sweep_waves_per_simd(ns, vgpr_per_slot(prec));
     // waves resident per SIMD when all N recipients are swept
     const double occ = std::min<double>(wps, (double)N * nw / 1024.0);
     const double ops = (f64 ? 4.19 : 4.0) * ns + 60.7;
@@ -110,7 +110,9 @@ double shape_cost(int32_t N, int prec, int ns, int nw) {
 // Cheapest shape by shape_cost; among shapes within 1% of the cheapest, the
 // one with the fewest waves (then the fewest slots). Depends on N and the
 // precision only, so a given problem always runs with the same summation
-// order.
+// order. The gradient first looks among the groups its prefetching adjoint
+// kernel runs (grad_max_waves), costed with that kernel's occupancy; only
+// when none of them places N does it take the sweep's wider groups.
 bool choose_shape(int32_t N, int prec, Shape *out, bool grad = false) {
     if (const char *env = std::getenv("LS_FORCE_SHAPE")) {
         int ns = 0, nw = 0;
@@ -119,17 +121,26 @@ bool choose_shape(int32_t N, int prec, Shape *out, bool grad = false) {
             return true;
         }
     }
-    double best = 1e300;
-    for (int nw = 1; nw <= lsk::kMaxWaves; ++nw)
-        for (int ns : menu(prec, grad))
-            if (shape_fits(N, prec, ns, nw)) best = std::min(best, shape_cost(N, prec, ns, nw));
-    if (best >= 1e300) return false;
-    for (int nw = 1; nw <= lsk::kMaxWaves; ++nw)
-        for (int ns : menu(prec, grad))
-            if (shape_fits(N, prec, ns, nw) && shape_cost(N, prec, ns, nw) <= best * 1.01) {
-                *out = Shape{ns, nw};
-                return true;
-            }
+    const int vps = vgpr_per_slot(prec);
+    for (int pass = grad ? 0 : 1; pass < 2; ++pass) {
+        auto ok = [&](int ns, int nw) {
+            return shape_fits(N, prec, ns, nw) && (pass == 1 || nw <= lsk::grad_max_waves(ns, vps));
+        };
+        auto cost = [&](int ns, int nw) {
+            return shape_cost(N, prec, ns, nw, pass == 0 ? lsk::grad_waves_per_simd(ns, vps) : 0);
+        };
+        double best = 1e300;
+        for (int nw = 1; nw <= lsk::kMaxWaves; ++nw)
+            for (int ns : menu(prec, grad))
+                if (ok(ns, nw)) best = std::min(best, cost(ns, nw));
+        if (best >= 1e300) continue;
+        for (int nw = 1; nw <= lsk::kMaxWaves; ++nw)
+            for (int ns : menu(prec, grad))
+                if (ok(ns, nw) && cost(ns, nw) <= best * 1.01) {
+                    *out = Shape{ns, nw};
+                    return true;
+                }
+    }
     return false;
 }
 
@@ -540,6 +551,7 @@ ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R
     ga.Hr = m->Hr;
     ga.rho = m->L > 1 ? m->rho : reinterpret_cast<const double *>(m->Hr);
     ga.coef_fwd32 = coef_table(m, LS_FP32, 0);
+    ga.coef_bwd32 = coef_table(m, LS_FP32, 1);
     ga.recipients = rec;
     ga.hr_stride = m->hr_stride;
     ga.N = m->N;

@@ -141,10 +141,16 @@ __device__ __forceinline__ T block_sum(T x, T *red, int &parity, int wave, int n
     return lanes_sum<MAXW>(p);
 }
 
-// Four sums at once with one barrier (same fixed trees as block_sum).
-// `red` holds 2 * 4 * MAXW entries.
+// Four sums at once with one barrier (same fixed trees as block_sum). Wave w
+// writes its partial of sum q to entry 16 q + w of a double-buffered array
+// of kRedStride entries per buffer; lane k of every wave then reads entry k,
+// so 16-lane DPP row q holds the partials of sum q, and the butterflies of
+// lanes_sum, applied to all four rows at once, leave each total in the first
+// lane of its row. The additions and their order are those of a pairwise
+// tree over the wave partials.
 template <int MAXW, class T>
 __device__ __forceinline__ void block_sum4(T (&x)[4], T *red, int &parity, int wave) {
+    static_assert(MAXW <= 16, "cross-wave sums cover one 16-lane DPP row");
     T w[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) w[q] = wave_sum(x[q]);
@@ -153,31 +159,39 @@ __device__ __forceinline__ void block_sum4(T (&x)[4], T *red, int &parity, int w
         for (int q = 0; q < 4; ++q) x[q] = w[q];
         return;
     }
-    T *buf = red + parity * 4 * MAXW;
+    T *buf = red + parity * kRedStride;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) buf[q * MAXW + wave] = w[q];
+    for (int q = 0; q < 4; ++q) buf[16 * q + wave] = w[q];
     __syncthreads();
+    T p = buf[threadIdx.x & 63];
+    if constexpr (sizeof(T) == 4) {
+        if constexpr (MAXW > 1) p += dpp_f32<0xB1>(p);
+        if constexpr (MAXW > 2) p += dpp_f32<0x4E>(p);
+        if constexpr (MAXW > 4) p += dpp_f32<0x12C>(p);
+        if constexpr (MAXW > 8) p += dpp_f32<0x128>(p);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        T p[MAXW];
+        for (int q = 0; q < 4; ++q)
+            x[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p), 16 * q));
+    } else {
+        if constexpr (MAXW > 1) p += dpp_f64<0xB1>(p);
+        if constexpr (MAXW > 2) p += dpp_f64<0x4E>(p);
+        if constexpr (MAXW > 4) p += dpp_f64<0x12C>(p);
+        if constexpr (MAXW > 8) p += dpp_f64<0x128>(p);
 #pragma unroll
-        for (int k = 0; k < MAXW; ++k) p[k] = buf[q * MAXW + k];
-#pragma unroll
-        for (int h = 1; h < MAXW; h *= 2)
-#pragma unroll
-            for (int k = 0; k + h < MAXW; k += 2 * h) p[k] += p[k + h];
-        x[q] = p[0];
+        for (int q = 0; q < 4; ++q) {
+            const int lo = __builtin_amdgcn_readlane(__double2loint(p), 16 * q);
+            const int hi = __builtin_amdgcn_readlane(__double2hiint(p), 16 * q);
+            x[q] = __hiloint2double(hi, lo);
+        }
     }
     parity ^= 1;
 }
 
-// Zero both buffers of a block_sum array (2 * kRedStride entries) or of a
-// block_sum4 array (2 * 4 * MAXW entries, NV = 4); call once before the first
-// use, followed by a barrier.
-template <int MAXW, class T, int NV = 1>
+// Zero both buffers of a block_sum or block_sum4 array (2 * kRedStride
+// entries); call once before the first use, followed by a barrier.
+template <int MAXW, class T>
 __device__ __forceinline__ void block_sum_init(T *red) {
-    constexpr int n = NV == 1 ? 2 * kRedStride : 2 * NV * MAXW;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) red[k] = (T)0;
+    for (int k = threadIdx.x; k < 2 * kRedStride; k += blockDim.x) red[k] = (T)0;
 }
 
 // ---------------------------------------------------------------------------

@@ -47,25 +47,28 @@ struct SweepArgs {
     double bmul;          // forward: kappa / (N-1); backward: kappa
     double log_off;       // per-step log offset: fwd -log(kappa), bwd -log((N-1) kappa),
                           // plus the emission unit's log (see sweep_emissions)
+    int64_t c_off;        // keep-alpha mode (gradient recompute): element offset, from
+                          // the snapshot array, of the [t - l0][R] c of each step
     int32_t tgt_l[kMaxTargets];    // variant of each visited target, travel order
     int32_t tgt_out[kMaxTargets];  // its index k in the [T] output arrays
 };
 
 // The emission pair a sweep multiplies by, from the form (1-H)(1-2mu)+mu of
 // appendix A.3 evaluated in FP64. The FP64 sweep uses the emissions as they
-// are. Sweeps in FP32 arithmetic use both divided by the match value 1-mu:
-// the match factor is then exactly 1 and adds no rounding to most cells,
-// where the rounded 1-mu would bias every step's sum the same way (a
-// log-likelihood error growing with L). Dividing every step's emissions by
-// one constant only rescales the vectors, so its log (`log_unit`) is added
-// to the per-step log offset in FP64.
+// are. Sweeps in FP32 arithmetic use both divided by the larger one (the
+// match value 1-mu for every mu <= 1/2): that factor is then exactly 1 and
+// adds no rounding to most cells, where the rounded 1-mu would bias every
+// step's sum the same way (a log-likelihood error growing with L). Dividing
+// every step's emissions by one constant only rescales the vectors, so its
+// log (`log_unit`) is added to the per-step log offset in FP64.
 struct Emissions {
     double match, mis, log_unit;
 };
 inline Emissions sweep_emissions(double mu, bool fp32_arith) {
     const double omu = (1.0 - 2.0 * mu) + mu;
     if (!fp32_arith) return Emissions{omu, mu, 0.0};
-    return Emissions{1.0, mu / omu, std::log(omu)};
+    if (omu >= mu) return Emissions{1.0, mu / omu, std::log(omu)};
+    return Emissions{omu / mu, 1.0, std::log(mu)};
 }
 
 // Kernel shape: 64-donor register slots per wave, waves per recipient.
@@ -88,6 +91,22 @@ __host__ __device__ constexpr int max_waves_for(int nslot, int vgpr_per_slot) {
     return w > kMaxWaves ? kMaxWaves : (w < 1 ? 1 : w);
 }
 
+// Largest group of the adjoint kernel that reads alpha ahead: per wave it
+// holds y, the alpha of the current pair of variants and of the next, and
+// the temporaries of two steps; 7 registers per slot plus 28 (FP32), 14.5
+// per slot plus 40 (FP64), fitted to the compiler's allocations, so that
+// the occupancy the shape choice assumes is the one the kernel gets.
+__host__ __device__ constexpr int grad_waves_per_simd(int nslot, int vgpr_per_slot) {
+    int need = vgpr_per_slot == 2 ? (29 * nslot + 80) / 2 : 7 * nslot + 28;
+    need = (need + 7) / 8 * 8;
+    int per_simd = 512 / need;  // 0: one wave does not fit, no narrow kernel
+    return per_simd > 8 ? 8 : per_simd;
+}
+__host__ __device__ constexpr int grad_max_waves(int nslot, int vgpr_per_slot) {
+    int w = 4 * grad_waves_per_simd(nslot, vgpr_per_slot);
+    return w > kMaxWaves ? kMaxWaves : w;
+}
+
 // Waves per SIMD the sweep kernel is compiled for (amdgpu_waves_per_eu): the
 // register file of one SIMD (512 VGPRs per lane) over the resident vector
 // plus a per-wave allowance. Holding the compiler to it keeps the common
@@ -99,6 +118,15 @@ __host__ __device__ constexpr int sweep_waves_per_simd(int nslot, int vgpr_per_s
     need = (need + 7) / 8 * 8;
     int w = 512 / need;
     return w > 8 ? 8 : (w < 1 ? 1 : w);
+}
+
+// Slot count whose sweep_waves_per_simd budget the sweep kernel is compiled
+// for. Keeping alpha at every variant (the gradient's recompute) holds more
+// registers: in FP32 about two per slot (measured).
+__host__ __device__ constexpr int sweep_budget_slots(int nslot, int vgpr_per_slot, bool every) {
+    if (!every) return nslot;
+    if (vgpr_per_slot == 1 && 2 * nslot - 12 > nslot + 16) return 2 * nslot - 12;
+    return nslot + 16;
 }
 
 // Slot counts instantiated per precision. Every shape the host picks uses
@@ -170,7 +198,9 @@ struct GradLayout {
     size_t off_ll;      // double [R]  per-recipient log-likelihood
     size_t off_status;  // uint32 [R]
     size_t off_ckpt;    // [R][nseg][N] forward vectors at checkpoints (gradient)
-    size_t off_seg;     // [R][seg][N]  forward vectors inside one segment
+    size_t off_seg;     // [(seg-1)/2][R][N] forward vectors at even offsets
+                        // 2, 4, .. from the segment's checkpoint
+    size_t off_cval;    // [seg][R] c of the forward step at each offset 1, 2, ..
     size_t off_grow;    // double [L-1][R] per-recipient d log P / d rho
     size_t off_gmu;     // double [R]
     size_t off_lsc;     // double [R] scratch log scale of the recompute sweeps
@@ -185,6 +215,7 @@ struct GradArgs {
     const uint64_t *Hr;
     const double *rho;
     const float *coef_fwd32;  // FP32 forward coefficient table
+    const float *coef_bwd32;  // FP32 backward coefficient table
     const int32_t *recipients;
     int64_t hr_stride;
     int32_t N, L, NF, R;

@@ -67,13 +67,14 @@ __device__ __forceinline__ SpecSlot special_slot(int q, int NF, int N, int g, bo
     return sp;
 }
 
-// EVERY (forward only, kappa = 1): keep alpha at every variant l0+1 .. t, in
-// snap rows tgt_out[0], tgt_out[0]+1, ... (the segment recompute of the
-// gradient); the target list is not used.
+// EVERY (forward only, kappa = 1; the segment recompute of the gradient):
+// for the variants l0+1 .. t keep alpha at even offsets k = l - l0 (snap row
+// tgt_out[0] + k/2 - 1) and the c of every step (at snap + c_off, [k-1][R]);
+// the target list is not used.
 template <class PT, int NSLOT, int DIR, bool EVERY = false>
 __global__ void __launch_bounds__(64 * max_waves_for(NSLOT, PT::vgpr_per_slot))
-__attribute__((amdgpu_waves_per_eu(sweep_waves_per_simd(NSLOT + (EVERY ? 16 : 0),
-                                                         PT::vgpr_per_slot))))
+__attribute__((amdgpu_waves_per_eu(
+    sweep_waves_per_simd(sweep_budget_slots(NSLOT, PT::vgpr_per_slot, EVERY), PT::vgpr_per_slot))))
 sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
              const float *__restrict__ coef, const int32_t *__restrict__ recipients, typename PT::ST *__restrict__ state,
              double *__restrict__ log_scale, uint32_t *__restrict__ status,
@@ -362,8 +363,12 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
                                    : 0x7ffffff0;
             }
             const int voff = lane * (int)sizeof(IO);
-            IO *dst = snap + ((int64_t)a.tgt_out[0] * a.R + r) * N;
-            const int64_t dstep = (int64_t)a.R * N;
+            IO *const seg0 = snap + ((int64_t)a.tgt_out[0] * a.R + r) * N;
+            // c of every step, [step][R]; one lane of the group stores it (the
+            // others get an offset past the record, so their stores drop)
+            const rsrc_t rs_c =
+                make_rsrc(snap + a.c_off, (uint32_t)((a.t - a.l0) * a.R * (int)sizeof(IO)));
+            const int c_voff = threadIdx.x == 0 ? r * (int)sizeof(IO) : 0x7ffffff0;
             T A_nx, B_nx;
             coefs_at(l <= lmax ? l : lmax, A_nx, B_nx);
             uint64_t w_nx = self_word(l <= lmax ? l : lmax);
@@ -375,12 +380,19 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
                 coefs_at(ln, A_nx, B_nx);
                 w_nx = self_word(ln);
                 T part = step(l, wb, c, B);
+                buf_store((IO)c, rs_c, c_voff, (l - a.l0 - 1) * a.R * (int)sizeof(IO));
                 S = block_sum<MAXW>(part, red, parity, wave, nwaves);
                 c_nx = coef_c(A_nx, S);
                 account(S);
                 // alpha^l (exactly 0 on the recipient's lane and on lanes
-                // without a donor), unscaled: kappa = 1 in this mode
-                const rsrc_t rs = make_rsrc(dst, (uint32_t)N * sizeof(IO));
+                // without a donor), unscaled: kappa = 1 in this mode. Only
+                // even offsets k = l - l0 from the checkpoint are kept, in row
+                // k/2 - 1; at odd offsets the record is empty and the stores
+                // drop (the adjoint pass derives those vectors with one step)
+                const int k = l - a.l0;
+                const rsrc_t rs =
+                    make_rsrc(seg0 + (int64_t)((k >> 1) - 1 + (k & 1)) * a.R * N,
+                              (k & 1) ? 0u : (uint32_t)N * (uint32_t)sizeof(IO));
                 const int rb = opaque(reg_base);
 #pragma unroll
                 for (int s = 0; s < NSLOT; ++s) {
@@ -395,7 +407,6 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
                 // keep the stores of alpha^l ahead of the next update: moved
                 // past it, they would hold a second copy of the column live
                 __builtin_amdgcn_sched_barrier(0);
-                dst += dstep;
             }
         } else for (;;) {
             const int lend = kt < a.nt ? a.tgt_l[kt] : a.t;

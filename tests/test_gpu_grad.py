@@ -9,7 +9,7 @@ import pytest
 import oracle
 from lsinputs import make_inputs, pack_haplotypes, rho_from_spacings, seeded_recipients
 
-from _gpu import F32_LOGLIK_RTOL, need_gpu
+from _gpu import F32_LOGLIK_RTOL, forced_shape, need_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -71,6 +71,62 @@ def test_gradient_vs_oracle(ls, N, L, prec):
         scale = max(np.abs(gr).max(), 1.0)
         assert np.abs(g_rho - gr).max() <= 1e-6 * scale
         assert abs(g_mu - gm) <= 1e-6 * max(abs(gm), 1.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gradient_mu_above_one_half(ls, prec):
+    """mu = 0.7: the FP32 sweeps divide both emissions by mu instead of 1-mu."""
+    N, L = 50, 120
+    H, rho, _ = _case(N, L, seed=70)
+    mu = 0.7
+    rec = np.arange(N, dtype=np.int32)
+    ll, gr, gm = _oracle_sum(H, N, L, rho, mu, rec)
+    out = ls.loglik_grad(ls.Model(H, N, rho, mu), None, prec, grad=True)
+    tol_ll, tol_g = (1e-12, 1e-10) if prec == "fp64" else (F32_LOGLIK_RTOL, 1e-6)
+    assert abs(float(out["pac"].item()) - ll) <= tol_ll * abs(ll)
+    assert np.abs(out["grad_rho"].cpu().numpy() - gr).max() <= tol_g * max(np.abs(gr).max(), 1.0)
+    assert abs(float(out["grad_mu"].item()) - gm) <= tol_g * max(abs(gm), 1.0)
+
+
+def _check_against_oracle(ls, H, N, L, rho, mu, rec, prec):
+    g_ref = oracle.run_gradient(H, N, L, rho, mu, rec)
+    ll, gr, gm = g_ref["loglik"].sum(), g_ref["grad_rho"].sum(axis=0), g_ref["grad_mu"].sum()
+    out = ls.loglik_grad(ls.Model(H, N, rho, mu), rec, prec, grad=True)
+    tol_ll, tol_g = (1e-12, 1e-10) if prec == "fp64" else (F32_LOGLIK_RTOL, 1e-6)
+    assert abs(float(out["pac"].item()) - ll) <= tol_ll * abs(ll)
+    # Each component sums one term per recipient (per variant too, for mu),
+    # and the terms cancel: the rounding of a term scales with its own size
+    # (for rho with pi Sa Sy and d before their difference is taken; for mu,
+    # the mismatch share M is amplified by 1/mu). So errors are bounded
+    # relative to the sum of the recipients' term magnitudes.
+    if L > 1:
+        g = out["grad_rho"].cpu().numpy()
+        rho_scale = max(np.abs(g_ref["grad_rho"]).sum(axis=0).max(), 1.0)
+        assert np.abs(g - gr).max() <= tol_g * rho_scale
+    mu_scale = max(np.abs(g_ref["grad_mu"]).sum(), 1.0)
+    assert abs(float(out["grad_mu"].item()) - gm) <= tol_g * mu_scale
+
+
+@pytest.mark.parametrize("L", [1, 2, 7, 10])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gradient_short_segments(ls, L, prec):
+    """Segments of ceil(sqrt(L)) variants; L = 7 ends in a one-variant
+    segment, L = 10 in a two-variant one, and the pass walks each segment in
+    pairs of variants whose first may be the last variant of all."""
+    N = 40
+    H, rho, mu = _case(N, L, seed=N + L)
+    _check_against_oracle(ls, H, N, L, rho, mu, np.arange(N, dtype=np.int32), prec)
+
+
+@pytest.mark.parametrize("prec,N,ns,nw", [("fp32", 10000, 16, 13), ("fp64", 4000, 8, 13)])
+def test_gradient_wide_groups(ls, prec, N, ns, nw):
+    """Groups wider than the prefetching adjoint kernel allows run its wide
+    variant (used at the largest N); forced here on a few recipients."""
+    L = 61
+    H, rho, mu = _case(N, L, seed=N)
+    rec = np.array([0, 63, N // 2, N - 1], np.int32)
+    with forced_shape(ns, nw):
+        _check_against_oracle(ls, H, N, L, rho, mu, rec, prec)
 
 
 def test_gradient_recipient_subset(ls):

@@ -346,6 +346,34 @@ def test_total_underflow_nan_columns(ls):
         assert ls.status_check(r["fwd"]) == ls.LS_WARN_NONFINITE
 
 
+@pytest.mark.parametrize("mu", [0.7, 1.0])
+def test_mutation_probability_above_one_half(ls, mu):
+    """For mu > 1/2 the mismatch emission is the larger one (the FP32 sweeps
+    then carry both emissions divided by mu). At mu = 1 only donors that
+    differ from the recipient at every variant keep mass between jumps; two
+    donors here are complements of recipients 0 and 3."""
+    N, L = 70, 40
+    rng = np.random.default_rng(31)
+    h = (rng.random((L, N)) < 0.5).astype(np.uint8)
+    h[:, 5] = 1 - h[:, 0]
+    h[:, 9] = 1 - h[:, 3]
+    H = pack_haplotypes(h)
+    rho = rho_from_spacings(rng.exponential(0.05, L - 1))
+    rec = np.array([0, 3, 40], np.int32)
+    targets = np.array([7, 30], np.int32)
+    ref = oracle.run_pass(H, N, L, rho, mu, rec, targets, want=("P",))
+    m = ls.Model(H, N, rho, mu)
+    for prec in ("fp64", "fp32", "f16"):
+        r = ls.decode(m, targets, prec, recipients=rec, want=("P",))
+        P, ll = _np(r["P"]), _np(r["fwd"].log_scale)
+        if prec == "fp64":
+            rel_close(P, ref["P"], F64_RTOL, F64_ATOL_PROB)
+            rel_close(ll, ref["llf"], F64_RTOL, F64_ATOL_LOG)
+        else:
+            assert np.abs(P - ref["P"]).max() <= F32_POST_ATOL
+            assert np.max(np.abs(ll - ref["llf"]) / np.abs(ref["llf"])) <= F32_LOGLIK_RTOL
+
+
 def test_model_mismatch_is_rejected(ls):
     N, L = 70, 10
     H, rho, mu = _random_case(N, L, seed=8)
