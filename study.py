@@ -2,16 +2,18 @@
 
     python study.py c4   gradient of the PAC log-likelihood (N = 2,000,
                          L = 50,000): time per gradient in FP32 and FP64,
-                         VALU and HBM rooflines of the pass, FP32 adjoint vs
-                         the FP64 oracle score on seeded recipients and vs
-                         central differences of the FP64 GPU PAC
+                         VALU and HBM rooflines of the pass, FP32 and FP64
+                         adjoint vs the FP64 oracle score over all recipients
+                         and vs central differences of the FP64 GPU PAC at 64
+                         seeded rho_l
     python study.py c3   precision study (N = 50,000, L = 20,000, rare-variant
                          mosaic, 20 targets): FP32 and FP16-stored posteriors
                          and log-likelihoods vs the FP64 oracle on seeded
                          recipients, and the decode time of all recipients
     python study.py c2   FP32 against FP64 on the benchmark workload (N = 10,000,
                          L = 100,000, 100 targets) over all recipients and
-                         targets: posterior and distance errors
+                         targets: posterior and distance errors; both GPU
+                         paths against the oracle on 256 seeded recipients
     python study.py c5   the share of one GPU of the large workload
                          (N = 100,000, L = 10,000, 5 targets): recipients
                          [0, 12,500) against all 100,000 donors, FP32 decode
@@ -56,6 +58,25 @@ def events():
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
+def _chunks(rec, size):
+    for lo in range(0, len(rec), size):
+        yield rec[lo:lo + size]
+
+
+def _oracle_pass(oracle, x, rec, targets, want, label, chunk=64):
+    """The oracle's pass over `rec` in chunks, with a progress line each."""
+    parts = []
+    t0 = time.perf_counter()
+    for sub in _chunks(rec, chunk):
+        parts.append(oracle.run_pass(x["H"], x["N"], x["L"], x["rho"], x["mu"], sub, targets,
+                                     want=want))
+        done = sum(len(p["llf"]) for p in parts)
+        log(f"{label} oracle: {done}/{len(rec)} recipients ({time.perf_counter() - t0:.0f} s)")
+    out = {k: np.concatenate([p[k] for p in parts], axis=1 if parts[0][k].ndim >= 2 else 0)
+           for k in parts[0]}
+    return out, time.perf_counter() - t0
+
+
 def study_c4(args):
     import torch
 
@@ -87,12 +108,13 @@ def study_c4(args):
         seg = int(np.ceil(np.sqrt(L)))
         esz = 4 if prec == "fp32" else 8
         # forward with checkpoints (4 ops/cell), per segment a forward
-        # recompute (4) and the adjoint pass (12: select, fma, mul, add for
-        # the backward vector; fma, add, fma, select+fma for d, Sa, M)
-        ops = 20.0 * cells
-        # segment buffer written by the recompute and read by the adjoint,
-        # plus checkpoints written once and read once
-        hbm = 2.0 * cells * esz + 2.0 * (L / seg) * N * N * esz
+        # recompute (4) and the adjoint pass (8: select, fma, mul, add for
+        # the backward vector; fma, add, select, fma for d, Sa and M; plus
+        # fma and mul on the half of the variants whose alpha it derives)
+        ops = 17.0 * cells
+        # alpha at every second variant written by the recompute and read by
+        # the adjoint, plus checkpoints written once and read once
+        hbm = 1.0 * cells * esz + 2.0 * (L / seg) * N * N * esz
         peak = VALU_PEAK if prec == "fp32" else VALU_PEAK_F64
         out[prec] = {"gradient_ms": ms, "loglik_only_ms": ms_ll,
                      "cells_per_s": cells / (ms / 1e3),
@@ -106,21 +128,28 @@ def study_c4(args):
     out["fp32_vs_fp64_grad_rho_normwise"] = float(np.abs(gr32 - gr64).max() / np.abs(gr64).max())
     out["fp32_vs_fp64_grad_mu_rel"] = float(abs(g32["grad_mu"].item() - g64["grad_mu"].item())
                                            / abs(g64["grad_mu"].item()))
-    # oracle score on seeded recipients (full L)
-    rec = seeded_recipients(N, args.recipients, seed=404)
+    # the oracle's exact score over the recipients (all of them by default),
+    # summed chunk by chunk (it holds an L x N FP64 table per thread)
+    rec = (np.arange(N, dtype=np.int32) if args.recipients >= N
+           else seeded_recipients(N, args.recipients, seed=404))
     t0 = time.perf_counter()
-    ref = oracle.run_gradient(x["H"], N, L, rho, mu, rec)
+    ll_ref, rg, gm_ref, done = 0.0, np.zeros(L - 1), 0.0, 0
+    for sub in _chunks(rec, 250):
+        ref = oracle.run_gradient(x["H"], N, L, rho, mu, sub)
+        ll_ref += ref["loglik"].sum()
+        rg += ref["grad_rho"].sum(axis=0)
+        gm_ref += ref["grad_mu"].sum()
+        done += len(sub)
+        log(f"c4 oracle: {done}/{len(rec)} recipients ({time.perf_counter() - t0:.0f} s)")
     dt = time.perf_counter() - t0
     gsub = ls.loglik_grad(model, rec, "fp32", grad=True)
     gsub64 = ls.loglik_grad(model, rec, "fp64", grad=True)
-    rg = ref["grad_rho"].sum(axis=0)
     for name, gg in (("fp32", gsub), ("fp64", gsub64)):
         out[f"{name}_vs_oracle_grad_rho_normwise"] = float(
             np.abs(gg["grad_rho"].cpu().numpy() - rg).max() / np.abs(rg).max())
-        out[f"{name}_vs_oracle_grad_mu_rel"] = float(
-            abs(gg["grad_mu"].item() - ref["grad_mu"].sum()) / abs(ref["grad_mu"].sum()))
-        out[f"{name}_vs_oracle_pac_rel"] = float(
-            abs(gg["pac"].item() - ref["loglik"].sum()) / abs(ref["loglik"].sum()))
+        out[f"{name}_vs_oracle_grad_mu_rel"] = float(abs(gg["grad_mu"].item() - gm_ref)
+                                                     / abs(gm_ref))
+        out[f"{name}_vs_oracle_pac_rel"] = float(abs(gg["pac"].item() - ll_ref) / abs(ll_ref))
     out["oracle_recipients"] = len(rec)
     out["oracle_seconds"] = dt
     # central differences of the FP64 GPU PAC (all recipients), h = 1e-6 rho_l
@@ -165,9 +194,7 @@ def study_c3(args):
     N, L, targets = x["N"], x["L"], x["targets"]
     model = ls.Model(x["H"], N, x["rho"], x["mu"])
     rec = seeded_recipients(N, args.recipients, seed=3)
-    t0 = time.perf_counter()
-    ref = oracle.run_pass(x["H"], N, L, x["rho"], x["mu"], rec, targets, want=("P", "E"))
-    dt = time.perf_counter() - t0
+    ref, dt = _oracle_pass(oracle, x, rec, targets, ("P", "E"), "c3")
     out = {"study": "c3 precision", "N": N, "L": L, "targets": len(targets),
            "oracle_recipients": len(rec), "oracle_seconds": dt}
     for prec in ("fp32", "f16"):
@@ -238,9 +265,7 @@ def study_c5(args):
     status = ls.status_check(fwd)
     out["nonfinite"] = int(status)
     rec = seeded_recipients(R, args.recipients, seed=5)
-    t0 = time.perf_counter()
-    ref = oracle.run_pass(x["H"], N, L, x["rho"], x["mu"], rec, targets, want=("P",))
-    out["oracle_seconds"] = time.perf_counter() - t0
+    ref, out["oracle_seconds"] = _oracle_pass(oracle, x, rec, targets, ("P",), "c5", chunk=32)
     out["oracle_recipients"] = len(rec)
     r = ls.decode(model, targets, "fp32", recipients=rec, want=("P",))
     out["max_abs_posterior_err_vs_oracle"] = float(
@@ -299,6 +324,28 @@ def study_c2(args):
            "eps_floor_decisions_differing": floor_diff,
            "half_distance_floor": floor_half,
            "seconds": time.perf_counter() - t0}
+    if args.recipients:
+        # both GPU paths against the oracle on seeded recipients, all targets
+        import oracle
+        from lsinputs import seeded_recipients
+        rec = seeded_recipients(N, args.recipients, seed=2212)
+        ref, dt = _oracle_pass(oracle, x, rec, targets, ("P",), "c2", chunk=32)
+        out["oracle_recipients"] = len(rec)
+        out["oracle_seconds"] = dt
+        for prec in ("fp64", "fp32"):
+            r = ls.decode(model, targets, prec, recipients=rec, want=("P",))
+            P = r["P"].double().cpu().numpy()
+            ll = r["fwd"].log_scale.cpu().numpy()
+            del r
+            err = np.abs(P - ref["P"])
+            out[f"{prec}_vs_oracle_max_abs_posterior_err"] = float(err.max())
+            if prec == "fp64":
+                out["fp64_vs_oracle_max_rel_posterior_err"] = float(
+                    np.max(err / np.maximum(np.abs(ref["P"]), 1e-300)))
+            out[f"{prec}_vs_oracle_max_rel_loglik_err"] = float(
+                np.max(np.abs(ll - ref["llf"]) / np.abs(ref["llf"])))
+            del P, err
+            log(f"c2 {prec} vs oracle: {out[f'{prec}_vs_oracle_max_abs_posterior_err']:.3e}")
     print(json.dumps(out), flush=True)
 
 
@@ -449,7 +496,7 @@ def main():
     ap.add_argument("which", choices=["c2", "c3", "c4", "c5", "emu"])
     ap.add_argument("--recipients", type=int, default=None,
                     help="seeded recipients checked against the oracle")
-    ap.add_argument("--fd", type=int, default=16, help="finite-difference components (c4)")
+    ap.add_argument("--fd", type=int, default=64, help="finite-difference components (c4)")
     ap.add_argument("--window", type=int, default=12_500, help="recipients per decode (c3)")
     ap.add_argument("--targets-per-window", type=int, default=20, help="targets per decode (c2)")
     ap.add_argument("--emu-n", type=int, default=5000, help="haplotypes (emu)")
@@ -461,16 +508,19 @@ def main():
         return
     import paper_2212_11403_amd as ls
     ls.load()
+    # default oracle samples: c2 and c3 256 seeded recipients, c4 all of
+    # them, c5 64 of the GPU's share
     if args.which == "c2":
+        args.recipients = 256 if args.recipients is None else args.recipients
         study_c2(args)
     elif args.which == "c4":
-        args.recipients = args.recipients or 64
+        args.recipients = args.recipients or 2000
         study_c4(args)
     elif args.which == "c3":
-        args.recipients = args.recipients or 128
+        args.recipients = args.recipients or 256
         study_c3(args)
     else:
-        args.recipients = args.recipients or 32
+        args.recipients = args.recipients or 64
         study_c5(args)
 
 
