@@ -561,6 +561,8 @@ ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R
     ga.seg = lay.seg;
     ga.nseg = lay.nseg;
     ga.mu = m->mu;
+    ga.chunk = sweep_chunk();
+    if (!choose_shape(m->N, prec, &ga.fwd_shape)) return LS_ERR_UNSUPPORTED;
     ga.ws = ws;
     ga.lay = lay;
     return dev(lsk::launch_grad(ga, (int)prec, sh, loglik, pac, grad_rho, grad_mu, st));

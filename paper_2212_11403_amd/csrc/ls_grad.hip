@@ -529,23 +529,30 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
             return prec == 0 ? launch_every<PrecF64>(p, a, sh, st)
                              : launch_every<PrecF32>(p, a, sh, st);
         }
-        return prec == 0 ? launch_sweep_f64_fwd(p, a, sh, st) : launch_sweep_f32_fwd(p, a, sh, st);
+        return prec == 0 ? launch_sweep_f64_fwd(p, a, ga.fwd_shape, st)
+                         : launch_sweep_f32_fwd(p, a, ga.fwd_shape, st);
     };
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ws + Ly.off_status), 0u, ga.R, st);
     if (e != hipSuccess) return e;
-    // 1. forward with checkpoints at l = k * seg; ll = log F^{L-1}
+    // 1. forward with checkpoints at l = k * seg; ll = log F^{L-1}. It runs
+    // with the sweep's own shape and in the launches a plain forward sweep
+    // makes (at most ga.chunk variants each, resuming from the table), so
+    // log P is bit-identical to that of the log-likelihood alone. A launch
+    // holds at most chunk / seg + 1 <= sqrt(chunk) + 1 checkpoints (with an
+    // oversized chunk, a launch ends at its 256th checkpoint).
     void *fstate = ws + Ly.off_state;
     double *ll = reinterpret_cast<double *>(ws + Ly.off_ll);
     std::vector<int32_t> tl(2 * kMaxTargets);
-    int l0 = -1;
-    for (int k0 = 0; k0 < ga.nseg; k0 += kMaxTargets) {
-        const int k1 = std::min(ga.nseg, k0 + kMaxTargets);
-        for (int k = k0; k < k1; ++k) {
-            tl[2 * (k - k0)] = k * ga.seg;
-            tl[2 * (k - k0) + 1] = k;
+    int l0 = -1, knext = 0;
+    while (l0 < ga.L - 1) {
+        int t = std::min(ga.L - 1, (l0 < 0 ? 0 : l0) + ga.chunk);
+        int nt = 0;
+        for (; knext < ga.nseg && knext * ga.seg <= t && nt < kMaxTargets; ++knext, ++nt) {
+            tl[2 * nt] = knext * ga.seg;
+            tl[2 * nt + 1] = knext;
         }
-        const int t = k1 == ga.nseg ? ga.L - 1 : (k1 - 1) * ga.seg;
-        e = sweep(0, l0, t, tl.data(), k1 - k0, fstate, ws + Ly.off_ckpt, ll);
+        if (knext < ga.nseg && knext * ga.seg <= t) t = tl[2 * (nt - 1)];
+        e = sweep(0, l0, t, tl.data(), nt, fstate, ws + Ly.off_ckpt, ll);
         if (e != hipSuccess) return e;
         l0 = t;
     }

@@ -220,6 +220,8 @@ struct GradArgs {
     int64_t hr_stride;
     int32_t N, L, NF, R;
     int32_t seg, nseg;
+    int32_t chunk;      // variants per launch of the checkpointing forward sweep
+    Shape fwd_shape;    // its shape: the one a plain forward sweep of N uses
     double mu;
     char *ws;
     GradLayout lay;

@@ -129,6 +129,20 @@ def test_gradient_wide_groups(ls, prec, N, ns, nw):
         _check_against_oracle(ls, H, N, L, rho, mu, rec, prec)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gradient_log_likelihood_equals_plain(ls, prec):
+    """The gradient's checkpointing forward sweep runs with the plain forward
+    sweep's shape and launches, so log P is the same bits with or without
+    the gradient (at several launches per sweep)."""
+    N, L = 300, 5000
+    H, rho, mu = _case(N, L, seed=77)
+    m = ls.Model(H, N, rho, mu)
+    g = ls.loglik_grad(m, None, prec, grad=True)
+    p = ls.loglik_grad(m, None, prec, grad=False)
+    assert np.array_equal(g["loglik"].cpu().numpy(), p["loglik"].cpu().numpy())
+    assert g["pac"].item() == p["pac"].item()
+
+
 def test_gradient_recipient_subset(ls):
     N, L = 100, 150
     H, rho, mu = _case(N, L, seed=3)
