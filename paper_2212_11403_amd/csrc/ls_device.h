@@ -83,6 +83,44 @@ __device__ __forceinline__ float wave_sum(float x) {
     return read_lane63(x);
 }
 
+// Four wave sums at once, each with the additions and order of wave_sum: the
+// four chains are interleaved stage by stage, so each DPP read comes three
+// instructions after the write it depends on and needs no wait states.
+__device__ __forceinline__ void wave_sum4(const float (&x)[4], float (&w)[4]) {
+    float a = x[0], b = x[1], c = x[2], d = x[3];
+    a += dpp_f32<0xB1>(a);
+    b += dpp_f32<0xB1>(b);
+    c += dpp_f32<0xB1>(c);
+    d += dpp_f32<0xB1>(d);
+    a += dpp_f32<0x4E>(a);
+    b += dpp_f32<0x4E>(b);
+    c += dpp_f32<0x4E>(c);
+    d += dpp_f32<0x4E>(d);
+    a += dpp_f32<0x124>(a);
+    b += dpp_f32<0x124>(b);
+    c += dpp_f32<0x124>(c);
+    d += dpp_f32<0x124>(d);
+    a += dpp_f32<0x128>(a);
+    b += dpp_f32<0x128>(b);
+    c += dpp_f32<0x128>(c);
+    d += dpp_f32<0x128>(d);
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "v_add_f32_dpp %2, %2, %2 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "v_add_f32_dpp %3, %3, %3 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "v_add_f32_dpp %2, %2, %2 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "v_add_f32_dpp %3, %3, %3 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "s_nop 1"
+        : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
+    w[0] = read_lane63(a);
+    w[1] = read_lane63(b);
+    w[2] = read_lane63(c);
+    w[3] = read_lane63(d);
+}
 __device__ __forceinline__ double wave_sum(double x) {
     x += dpp_f64<0xB1>(x);
     x += dpp_f64<0x4E>(x);
@@ -91,6 +129,11 @@ __device__ __forceinline__ double wave_sum(double x) {
     x += dpp_f64<0x142, 0xA, 0xF, false>(x);  // row_bcast:15 into rows 1, 3
     x += dpp_f64<0x143, 0xC, 0xF, false>(x);  // row_bcast:31 into rows 2, 3
     return read_lane63(x);
+}
+
+__device__ __forceinline__ void wave_sum4(const double (&x)[4], double (&w)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[q] = wave_sum(x[q]);
 }
 
 // Sum over the workgroup. Every wave returns the same value: each wave's
@@ -152,8 +195,7 @@ template <int MAXW, class T>
 __device__ __forceinline__ void block_sum4(T (&x)[4], T *red, int &parity, int wave) {
     static_assert(MAXW <= 16, "cross-wave sums cover one 16-lane DPP row");
     T w[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) w[q] = wave_sum(x[q]);
+    wave_sum4(x, w);
     if constexpr (MAXW == 1) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) x[q] = w[q];

@@ -1,6 +1,8 @@
 // Small kernels around the sweep: the internal row layout, the posterior /
 // half-distance pass over stored forward and backward vectors (eq. postprob,
 // eq. distmat) and the tiled symmetrisation of the distance matrix.
+#include <type_traits>
+
 #include "ls_device.h"
 
 namespace lsk {
@@ -93,6 +95,11 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
+// 16-byte vectors (native vector types: loads, stores and the streaming-store
+// builtin take them directly)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
 // ---------------------------------------------------------------------------
 // Posterior rows. One workgroup per row q (recipient recips[q % R]):
 //   Z = sum_j alpha_j beta_j,  p_j = alpha_j beta_j / Z (eps for all j != i
@@ -129,11 +136,99 @@ posterior_rows_kernel(const A *alpha, const B *__restrict__ beta, const int32_t 
     }
 }
 
+// The same rows with the products alpha_j beta_j held in registers, for
+// N <= 1024 K W (W = 16 / sizeof(T) elements per 16-byte vector, N a
+// multiple of W): alpha and beta are read once, with 16-byte loads, and P / E
+// are written with streaming stores. One workgroup of 1024 threads per row;
+// each thread keeps the products of the entries it writes.
+template <class T, int K>
+__global__ void __launch_bounds__(1024)
+posterior_rows_reg_kernel(const T *alpha, const T *__restrict__ beta,
+                          const int32_t *__restrict__ recips, int32_t R, int32_t N, T *P, T *E) {
+    using V = typename std::conditional<sizeof(T) == 4, f32x4, f64x2>::type;
+    constexpr int W = 16 / (int)sizeof(T);
+    __shared__ T red[16];
+    const int64_t q = blockIdx.x;
+    const int i = recips[q % R];
+    const T *ar = alpha + q * N;
+    const T *br = beta + q * N;
+    T w[K][W];
+    T z = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int j0 = ((int)threadIdx.x + 1024 * k) * W;
+        V a = {}, b = {};
+        if (j0 < N) {
+            a = *reinterpret_cast<const V *>(ar + j0);
+            b = *reinterpret_cast<const V *>(br + j0);
+        }
+        const T *xa = reinterpret_cast<const T *>(&a);
+        const T *xb = reinterpret_cast<const T *>(&b);
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            w[k][e] = xa[e] * xb[e];
+            z += w[k][e];
+        }
+    }
+    z = wave_sum(z);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[wave] = z;
+    __syncthreads();
+    T t[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) t[k] = red[k];
+#pragma unroll
+    for (int h = 1; h < 16; h *= 2)
+#pragma unroll
+        for (int k = 0; k + h < 16; k += 2 * h) t[k] += t[k + h];
+    const T Z = t[0];
+    const T eps = (T)2.220446049250313080847e-16;
+    const T invZ = (T)1 / Z;
+    T *Pr = P ? P + q * N : nullptr;
+    T *Er = E ? E + q * N : nullptr;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int j0 = ((int)threadIdx.x + 1024 * k) * W;
+        if (j0 >= N) continue;
+        V vp, ve;
+        T *xp = reinterpret_cast<T *>(&vp);
+        T *xe = reinterpret_cast<T *>(&ve);
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            const int j = j0 + e;
+            T pv = (Z == (T)0) ? eps : w[k][e] * invZ;
+            if (j == i) pv = 0;
+            const T qv = (pv < eps) ? eps : pv;  // NaN passes through
+            xp[e] = pv;
+            xe[e] = (j == i) ? (T)0 : (T)-0.5 * log(qv);
+        }
+        if (Pr) __builtin_nontemporal_store(vp, reinterpret_cast<V *>(Pr + j0));
+        if (Er) __builtin_nontemporal_store(ve, reinterpret_cast<V *>(Er + j0));
+    }
+}
+
 hipError_t launch_posterior_rows(const void *alpha, int alpha_half, const void *beta,
                                  int beta_half, const int32_t *recips, int32_t R, int64_t rows,
                                  int32_t N, int is_f64, void *P, void *E, hipStream_t st) {
     if (rows <= 0) return hipSuccess;
     const dim3 grid((unsigned)rows), block(256);
+    // rows that fit the register kernel: full-precision inputs, N a multiple
+    // of the vector width, at most 16 elements per thread, 16-byte aligned
+    auto aligned = [](const void *x) { return (reinterpret_cast<uintptr_t>(x) & 15) == 0; };
+    const int w = is_f64 ? 2 : 4;
+    const bool reg = !alpha_half && !beta_half && N % w == 0 && N <= 1024 * 16 &&
+                     aligned(alpha) && aligned(beta) && aligned(P) && aligned(E);
+    if (reg) {
+        if (is_f64)
+            hipLaunchKernelGGL((posterior_rows_reg_kernel<double, 8>), grid, dim3(1024), 0, st,
+                               (const double *)alpha, (const double *)beta, recips, R, N,
+                               (double *)P, (double *)E);
+        else
+            hipLaunchKernelGGL((posterior_rows_reg_kernel<float, 4>), grid, dim3(1024), 0, st,
+                               (const float *)alpha, (const float *)beta, recips, R, N,
+                               (float *)P, (float *)E);
+        return hipGetLastError();
+    }
     if (is_f64) {
         hipLaunchKernelGGL((posterior_rows_kernel<double, double, double, double>), grid, block, 0,
                            st, (const double *)alpha, (const double *)beta, recips, R, N,
@@ -152,47 +247,120 @@ hipError_t launch_posterior_rows(const void *alpha, int alpha_half, const void *
 
 // ---------------------------------------------------------------------------
 // D = E + E^T with a zero diagonal, T matrices of N x N, in place allowed.
-// Workgroup (bx, by, k) with by <= bx owns the tile pair (by, bx) / (bx, by):
-// it reads both 64 x 64 tiles into LDS before writing either, so no other
-// workgroup touches them and D may alias E.
-template <class X>
+// Workgroup (p, k) owns the tile pair (by, bx) / (bx, by), by <= bx, of
+// matrix k, where p counts the pairs of the upper triangle row by row: it
+// reads both 64 x 64 tiles into LDS before writing either, so no other
+// workgroup touches them and D may alias E. With VEC (N a multiple of the
+// 16-byte vector) every lane moves 16 bytes per load and store; D is written
+// with streaming stores (it is not read again here).
+__device__ __forceinline__ void tile_pair(int64_t p, int nb, int &by, int &bx) {
+    // first pair of row b: b nb - b (b - 1) / 2
+    const double a = 2.0 * nb + 1.0;
+    int b = (int)((a - sqrt(a * a - 8.0 * (double)p)) * 0.5);
+    auto first = [&](int r) { return (int64_t)r * nb - (int64_t)r * (r - 1) / 2; };
+    while (b > 0 && first(b) > p) --b;
+    while (b + 1 < nb && first(b + 1) <= p) ++b;
+    by = b;
+    bx = b + (int)(p - first(b));
+}
+
+template <class X, bool VEC>
 __global__ void __launch_bounds__(256)
-symmetrise_kernel(const X *E, X *D, int32_t N) {
-    const int bx = blockIdx.x, by = blockIdx.y;
-    if (by > bx) return;
+symmetrise_kernel(const X *E, X *D, int32_t N, int32_t nb) {
+    using V = typename std::conditional<sizeof(X) == 4, f32x4, f64x2>::type;
+    constexpr int W = 16 / (int)sizeof(X);  // elements per vector
+    int by, bx;
+    tile_pair(blockIdx.x, nb, by, bx);
     __shared__ X ta[64][65];
     __shared__ X tb[64][65];
-    const int64_t base = (int64_t)blockIdx.z * N * N;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+    const int64_t base = (int64_t)blockIdx.y * N * N;
     const int r0 = by * 64, c0 = bx * 64;
-    // ta = E[r0.., c0..], tb = E[c0.., r0..]
-    for (int rr = ty; rr < 64; rr += 4) {
-        const int r = r0 + rr, c = c0 + tx;
-        ta[rr][tx] = (r < N && c < N) ? E[base + (int64_t)r * N + c] : (X)0;
-        const int r2 = c0 + rr, c2 = r0 + tx;
-        tb[rr][tx] = (r2 < N && c2 < N) ? E[base + (int64_t)r2 * N + c2] : (X)0;
-    }
-    __syncthreads();
-    for (int rr = ty; rr < 64; rr += 4) {
-        const int r = r0 + rr, c = c0 + tx;
-        if (r < N && c < N) D[base + (int64_t)r * N + c] = (r == c) ? (X)0 : ta[rr][tx] + tb[tx][rr];
-        const int r2 = c0 + rr, c2 = r0 + tx;
-        if (by != bx && r2 < N && c2 < N)
-            D[base + (int64_t)r2 * N + c2] = tb[rr][tx] + ta[tx][rr];
+    if constexpr (VEC) {
+        // lane: W consecutive columns of one row; 256 / (64 / W) rows per pass
+        constexpr int CV = 64 / W, RP = 256 / CV;
+        const int cv = threadIdx.x % CV, rp = threadIdx.x / CV, cc = cv * W;
+        for (int rr = rp; rr < 64; rr += RP) {
+            V va = {}, vb = {};
+            if (r0 + rr < N && c0 + cc < N)
+                va = *reinterpret_cast<const V *>(E + base + (int64_t)(r0 + rr) * N + c0 + cc);
+            if (c0 + rr < N && r0 + cc < N)
+                vb = *reinterpret_cast<const V *>(E + base + (int64_t)(c0 + rr) * N + r0 + cc);
+            const X *xa = reinterpret_cast<const X *>(&va);
+            const X *xb = reinterpret_cast<const X *>(&vb);
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                ta[rr][cc + k] = xa[k];
+                tb[rr][cc + k] = xb[k];
+            }
+        }
+        __syncthreads();
+        for (int rr = rp; rr < 64; rr += RP) {
+            if (r0 + rr < N && c0 + cc < N) {
+                V o;
+                X *xo = reinterpret_cast<X *>(&o);
+#pragma unroll
+                for (int k = 0; k < W; ++k)
+                    xo[k] = (r0 + rr == c0 + cc + k) ? (X)0 : ta[rr][cc + k] + tb[cc + k][rr];
+                __builtin_nontemporal_store(
+                    o, reinterpret_cast<V *>(D + base + (int64_t)(r0 + rr) * N + c0 + cc));
+            }
+            if (by != bx && c0 + rr < N && r0 + cc < N) {
+                V o;
+                X *xo = reinterpret_cast<X *>(&o);
+#pragma unroll
+                for (int k = 0; k < W; ++k) xo[k] = tb[rr][cc + k] + ta[cc + k][rr];
+                __builtin_nontemporal_store(
+                    o, reinterpret_cast<V *>(D + base + (int64_t)(c0 + rr) * N + r0 + cc));
+            }
+        }
+    } else {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+        // ta = E[r0.., c0..], tb = E[c0.., r0..]
+        for (int rr = ty; rr < 64; rr += 4) {
+            const int r = r0 + rr, c = c0 + tx;
+            ta[rr][tx] = (r < N && c < N) ? E[base + (int64_t)r * N + c] : (X)0;
+            const int r2 = c0 + rr, c2 = r0 + tx;
+            tb[rr][tx] = (r2 < N && c2 < N) ? E[base + (int64_t)r2 * N + c2] : (X)0;
+        }
+        __syncthreads();
+        for (int rr = ty; rr < 64; rr += 4) {
+            const int r = r0 + rr, c = c0 + tx;
+            if (r < N && c < N) D[base + (int64_t)r * N + c] = (r == c) ? (X)0 : ta[rr][tx] + tb[tx][rr];
+            const int r2 = c0 + rr, c2 = r0 + tx;
+            if (by != bx && r2 < N && c2 < N)
+                D[base + (int64_t)r2 * N + c2] = tb[rr][tx] + ta[tx][rr];
+        }
     }
 }
 
 hipError_t launch_symmetrise(const void *E, void *D, int32_t N, int32_t T, int is_f64,
                              hipStream_t st) {
     if (T <= 0 || N <= 0) return hipSuccess;
+    if (T > 65535) return hipErrorInvalidValue;
     const int nb = (N + 63) / 64;
-    const dim3 grid(nb, nb, T), block(256);
-    if (is_f64)
-        hipLaunchKernelGGL((symmetrise_kernel<double>), grid, block, 0, st, (const double *)E,
-                           (double *)D, N);
-    else
-        hipLaunchKernelGGL((symmetrise_kernel<float>), grid, block, 0, st, (const float *)E,
-                           (float *)D, N);
+    const int64_t pairs = (int64_t)nb * (nb + 1) / 2;
+    if (pairs > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)pairs, (unsigned)T), block(256);
+    // vectors need rows that start on 16 bytes: N a multiple of the vector
+    // width and a 16-byte aligned base
+    const int w = is_f64 ? 2 : 4;
+    const bool vec = N % w == 0 && (reinterpret_cast<uintptr_t>(E) & 15) == 0 &&
+                     (reinterpret_cast<uintptr_t>(D) & 15) == 0;
+    if (is_f64) {
+        if (vec)
+            hipLaunchKernelGGL((symmetrise_kernel<double, true>), grid, block, 0, st,
+                               (const double *)E, (double *)D, N, nb);
+        else
+            hipLaunchKernelGGL((symmetrise_kernel<double, false>), grid, block, 0, st,
+                               (const double *)E, (double *)D, N, nb);
+    } else {
+        if (vec)
+            hipLaunchKernelGGL((symmetrise_kernel<float, true>), grid, block, 0, st,
+                               (const float *)E, (float *)D, N, nb);
+        else
+            hipLaunchKernelGGL((symmetrise_kernel<float, false>), grid, block, 0, st,
+                               (const float *)E, (float *)D, N, nb);
+    }
     return hipGetLastError();
 }
 

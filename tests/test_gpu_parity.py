@@ -312,17 +312,27 @@ def test_distance_matrix(ls, c1, c1_ref):
     assert np.array_equal(Dn, np.transpose(Dn, (0, 2, 1)))
 
 
-def test_symmetrise_ragged_tiles(ls):
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_symmetrise_ragged_tiles(ls, prec):
+    """D = E + E^T with a zero diagonal, bit-exact: ragged tiles, N a
+    multiple of the 16-byte vector or not, in place, and a base that is not
+    16-byte aligned (which takes the scalar path)."""
     import torch
-    for N in (1, 5, 64, 65, 130):
-        E = torch.rand((3, N, N), dtype=torch.float32, device="cuda")
-        En = E.cpu().numpy().astype(np.float64)
-        D = torch.empty_like(E)
-        ls.distance_symmetrise(E, D, "fp32")
-        ref = En + np.transpose(En, (0, 2, 1))
-        for k in range(3):
-            np.fill_diagonal(ref[k], 0.0)
-        assert np.array_equal(D.cpu().numpy().astype(np.float64), ref.astype(np.float32).astype(np.float64))
+    td = torch.float32 if prec == "fp32" else torch.float64
+    nd = np.float32 if prec == "fp32" else np.float64
+    for N in (1, 5, 64, 65, 128, 130, 132, 196, 300):
+        for inplace in (False, True):
+            for offset in (0, 1):
+                buf = torch.rand(3 * N * N + offset, dtype=td, device="cuda")
+                E = buf[offset:].view(3, N, N)
+                En = E.cpu().numpy().astype(np.float64)
+                D = E if inplace else torch.empty_like(E)
+                ls.distance_symmetrise(E, D, prec)
+                ref = En + np.transpose(En, (0, 2, 1))
+                for k in range(3):
+                    np.fill_diagonal(ref[k], 0.0)
+                got = D.cpu().numpy().astype(np.float64)
+                assert np.array_equal(got, ref.astype(nd).astype(np.float64)), (N, inplace, offset)
 
 
 def test_total_underflow_nan_columns(ls):
