@@ -1,0 +1,31 @@
+// The keep-alpha forward sweep of the gradient's segment recompute:
+// FP64, over the gradient's slot menu.
+#include "ls_grad_kernel.h"
+
+namespace lsk {
+
+template <int NSLOT>
+static hipError_t launch_every_one(const SweepPtrs &p, const SweepArgs &a, int nwaves,
+                                   hipStream_t st) {
+    using PT = PrecF64;
+    if (nwaves < 1 || nwaves > max_waves_for(NSLOT, PT::vgpr_per_slot)) return hipErrorInvalidValue;
+    if (a.nblk < 1 || a.r0 < 0 || a.r0 + a.nblk > a.R) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sweep_kernel<PT, NSLOT, 0, true>), dim3(a.nblk), dim3(64 * nwaves), 0, st,
+                       p.Hr, p.rho, p.coef, p.recipients, (typename PT::ST *)p.state,
+                       p.log_scale, p.status, (typename PT::IO *)p.snap, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_every_f64(const SweepPtrs &p, const SweepArgs &a, Shape sh, hipStream_t st) {
+    switch (sh.nslot) {
+#define LS_CASE(n) \
+    case n:        \
+        return launch_every_one<n>(p, a, sh.nwaves, st);
+        LS_MENU_GRAD(LS_CASE)
+#undef LS_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace lsk
