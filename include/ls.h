@@ -198,9 +198,20 @@ ls_status ls_distance_symmetrise(const void *E, void *D, int32_t N, int32_t T,
  * recipients: device, [R] (NULL = all N haplotypes in order, R must be N).
  * loglik: device [R] double (may be NULL); pac, grad_mu: device [1] double;
  * grad_rho: device [L-1] double. The sum over recipients is taken in a fixed
- * order, so results do not depend on scheduling.
- * workspace: device, >= ls_loglik_grad_workspace_bytes(m, R, prec) bytes.
- * Errors: LS_ERR_ARG, LS_ERR_WORKSPACE, LS_ERR_UNSUPPORTED, LS_ERR_DEVICE. */
+ * order, so results do not depend on scheduling. The gradient is the exact
+ * score (not a finite difference), computed with forward checkpoints every
+ * ceil(sqrt(L)) variants, a recompute of each segment and an adjoint pass;
+ * it is available for LS_FP64 and LS_FP32 (LS_FP32_F16STORE gives the
+ * log-likelihood only and returns LS_ERR_UNSUPPORTED if a gradient is
+ * asked for). log P and the sum are the same bits with or without the
+ * gradient.
+ * workspace: device, >= ls_loglik_grad_workspace_bytes(m, R, prec) bytes,
+ * 256-byte aligned; owned by the caller, contents undefined after the call.
+ * About e R N (1.5 sqrt(L) + 3) + 8 R L bytes (e = 4 for FP32, 8 for FP64):
+ * checkpoints, the kept half of one segment's forward vectors, the
+ * per-variant rho terms of every recipient.
+ * Errors: LS_ERR_ARG, LS_ERR_WORKSPACE (missing, too small or misaligned),
+ * LS_ERR_UNSUPPORTED, LS_ERR_DEVICE. */
 ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R,
                          ls_precision prec, double *loglik, double *pac, double *grad_rho,
                          double *grad_mu, void *workspace, size_t ws_bytes, void *stream);

@@ -90,3 +90,20 @@ def test_kernel_shapes_cover_every_size(lib):
             K = min(ns, 4)
             NW, NF = (N + 63) // 64, N // 64
             assert nw * (ns - K) <= NF and nw * ns >= NW, (prec, N, ns, nw)
+
+
+@pytest.mark.parametrize("N,L,R", [(2000, 50_000, 2000), (10_000, 100_000, 64), (300, 5000, 300)])
+def test_gradient_workspace_size(lib, N, L, R):
+    """ls_loglik_grad_workspace_bytes against the size the header states,
+    e R N (1.5 sqrt(L) + 3) + 8 R L bytes, within 2% (alignment and the
+    rounding of the segment length make up the rest). The query only reads
+    N, L and the model's validity fields, so a host-side struct serves."""
+    from paper_2212_11403_amd._lib import LsModel
+    m = LsModel()
+    m.N, m.L, m.hash, m.Hr = N, L, 1, 1
+    for prec, e in ((0, 8), (1, 4)):
+        got = lib.ls_loglik_grad_workspace_bytes(ctypes.byref(m), R, prec)
+        est = e * R * N * (1.5 * L ** 0.5 + 3) + 8 * R * L
+        assert abs(got - est) <= 0.02 * est, (prec, got, est)
+    m.hash = 0
+    assert lib.ls_loglik_grad_workspace_bytes(ctypes.byref(m), R, 1) == 0
