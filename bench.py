@@ -83,6 +83,32 @@ def copy_calibration():
           flush=True)
 
 
+def stream_probe():
+    """Practical HBM rates of plain streaming kernels (torch elementwise ops
+    over 4 GiB, event-timed), the yardstick for the HBM-bound kernels."""
+    import torch
+    n = 1 << 30
+    x = torch.rand(n, device="cuda")
+    y = torch.empty_like(x)
+
+    def rate(f, nbytes, reps=5):
+        f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        return nbytes / (e0.elapsed_time(e1) / reps / 1e3) / 1e12
+
+    out = {"unit": "TB/s",
+           "read_write_in_place": rate(lambda: x.mul_(1.0000001), 8 * n),
+           "read_write": rate(lambda: torch.mul(x, 1.0000001, out=y), 8 * n),
+           "write_only": rate(lambda: y.fill_(0.5), 4 * n)}
+    print(json.dumps(out), flush=True)
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -98,9 +124,14 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--err-recipients", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="print the HBM rates of plain streaming kernels and exit")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.stream_probe:
+        stream_probe()
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1 "

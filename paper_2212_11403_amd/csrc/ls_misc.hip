@@ -272,45 +272,74 @@ symmetrise_kernel(const X *E, X *D, int32_t N, int32_t nb) {
     int by, bx;
     tile_pair(blockIdx.x, nb, by, bx);
     __shared__ X ta[64][65];
-    __shared__ X tb[64][65];
+    __shared__ X tb[VEC ? 1 : 64][65];
     const int64_t base = (int64_t)blockIdx.y * N * N;
     const int r0 = by * 64, c0 = bx * 64;
     if constexpr (VEC) {
-        // lane: W consecutive columns of one row; 256 / (64 / W) rows per pass
-        constexpr int CV = 64 / W, RP = 256 / CV;
+        // lane: W consecutive columns of one row; RP rows per pass, IT passes.
+        // All loads of a lane are issued before the first wait; tiles fully
+        // inside the matrix (all but the last tile row and column) skip the
+        // bounds checks.
+        constexpr int CV = 64 / W, RP = 256 / CV, IT = 64 / RP;
         const int cv = threadIdx.x % CV, rp = threadIdx.x / CV, cc = cv * W;
-        for (int rr = rp; rr < 64; rr += RP) {
-            V va = {}, vb = {};
-            if (r0 + rr < N && c0 + cc < N)
-                va = *reinterpret_cast<const V *>(E + base + (int64_t)(r0 + rr) * N + c0 + cc);
-            if (c0 + rr < N && r0 + cc < N)
-                vb = *reinterpret_cast<const V *>(E + base + (int64_t)(c0 + rr) * N + r0 + cc);
-            const X *xa = reinterpret_cast<const X *>(&va);
-            const X *xb = reinterpret_cast<const X *>(&vb);
+        const bool full = r0 + 64 <= N && c0 + 64 <= N;
+        const X *ea = E + base + (int64_t)(r0 + rp) * N + c0 + cc;
+        const X *eb = E + base + (int64_t)(c0 + rp) * N + r0 + cc;
+        V va[IT], vb[IT];
+        if (full) {
 #pragma unroll
-            for (int k = 0; k < W; ++k) {
-                ta[rr][cc + k] = xa[k];
-                tb[rr][cc + k] = xb[k];
+            for (int it = 0; it < IT; ++it) {
+                va[it] = *reinterpret_cast<const V *>(ea + (int64_t)it * RP * N);
+                vb[it] = *reinterpret_cast<const V *>(eb + (int64_t)it * RP * N);
+            }
+        } else {
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int rr = rp + it * RP;
+                va[it] = (r0 + rr < N && c0 + cc < N)
+                             ? *reinterpret_cast<const V *>(ea + (int64_t)it * RP * N)
+                             : V{};
+                vb[it] = (c0 + rr < N && r0 + cc < N)
+                             ? *reinterpret_cast<const V *>(eb + (int64_t)it * RP * N)
+                             : V{};
             }
         }
+        // Both tiles are now in registers, so D (which may alias E) can be
+        // written at once. The transposed operand goes through one LDS tile
+        // used twice: tile b for the first output, then tile a.
+#pragma unroll
+        for (int it = 0; it < IT; ++it)
+#pragma unroll
+            for (int k = 0; k < W; ++k) ta[rp + it * RP][cc + k] = vb[it][k];
         __syncthreads();
-        for (int rr = rp; rr < 64; rr += RP) {
-            if (r0 + rr < N && c0 + cc < N) {
-                V o;
-                X *xo = reinterpret_cast<X *>(&o);
+        X *da = D + base + (int64_t)(r0 + rp) * N + c0 + cc;
+        X *db = D + base + (int64_t)(c0 + rp) * N + r0 + cc;
 #pragma unroll
-                for (int k = 0; k < W; ++k)
-                    xo[k] = (r0 + rr == c0 + cc + k) ? (X)0 : ta[rr][cc + k] + tb[cc + k][rr];
-                __builtin_nontemporal_store(
-                    o, reinterpret_cast<V *>(D + base + (int64_t)(r0 + rr) * N + c0 + cc));
-            }
-            if (by != bx && c0 + rr < N && r0 + cc < N) {
-                V o;
-                X *xo = reinterpret_cast<X *>(&o);
+        for (int it = 0; it < IT; ++it) {
+            const int rr = rp + it * RP;
+            V o;
 #pragma unroll
-                for (int k = 0; k < W; ++k) xo[k] = tb[rr][cc + k] + ta[cc + k][rr];
-                __builtin_nontemporal_store(
-                    o, reinterpret_cast<V *>(D + base + (int64_t)(c0 + rr) * N + r0 + cc));
+            for (int k = 0; k < W; ++k)
+                o[k] = (r0 + rr == c0 + cc + k) ? (X)0 : va[it][k] + ta[cc + k][rr];
+            if (full || (r0 + rr < N && c0 + cc < N))
+                __builtin_nontemporal_store(o, reinterpret_cast<V *>(da + (int64_t)it * RP * N));
+        }
+        if (by != bx) {
+            __syncthreads();
+#pragma unroll
+            for (int it = 0; it < IT; ++it)
+#pragma unroll
+                for (int k = 0; k < W; ++k) ta[rp + it * RP][cc + k] = va[it][k];
+            __syncthreads();
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int rr = rp + it * RP;
+                V o;
+#pragma unroll
+                for (int k = 0; k < W; ++k) o[k] = vb[it][k] + ta[cc + k][rr];
+                if (full || (c0 + rr < N && r0 + cc < N))
+                    __builtin_nontemporal_store(o,
+                                                reinterpret_cast<V *>(db + (int64_t)it * RP * N));
             }
         }
     } else {
