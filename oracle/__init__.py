@@ -49,6 +49,10 @@ def bind(path: str):
     lib.lso_gradient.restype = ctypes.c_int
     lib.lso_symmetrise.argtypes = [P, i32, P]
     lib.lso_symmetrise.restype = None
+    lib.lso_calc_rho.argtypes = [P, i32, f64, f64, P]
+    lib.lso_calc_rho.restype = None
+    lib.lso_rho_map_grad.argtypes = [P, i32, f64, f64, P, P, P]
+    lib.lso_rho_map_grad.restype = None
     lib.lso_version.restype = ctypes.c_char_p
     return lib
 
@@ -139,6 +143,29 @@ def distances(H, N, L, rho, mu, targets, nthreads=None):
     res = run_pass(H, N, L, rho, mu, np.arange(N, dtype=np.int32), targets, want=("E",),
                    nthreads=nthreads)
     return np.stack([symmetrise(res["E"][k]) for k in range(len(targets))])
+
+
+def calc_rho(cM, s=1.0, gamma=1.0, lib=None):
+    """rho_l = 1 - exp(-s (cM_l / 100)^gamma) (eq. rho; cM in centimorgans)."""
+    lib = lib or _load()
+    cM = np.ascontiguousarray(cM, dtype=np.float64)
+    rho = np.empty_like(cM)
+    lib.lso_calc_rho(_ptr(cM), cM.size, float(s), float(gamma), _ptr(rho))
+    return rho
+
+
+def rho_map_grad(cM, s, gamma, grad_rho, lib=None):
+    """(d/ds, d/dgamma) of a function whose gradient w.r.t. rho = calc_rho(cM,
+    s, gamma) is grad_rho."""
+    lib = lib or _load()
+    cM = np.ascontiguousarray(cM, dtype=np.float64)
+    g = np.ascontiguousarray(grad_rho, dtype=np.float64)
+    if g.size != cM.size:
+        raise ValueError("grad_rho and cM differ in length")
+    gs, gg = ctypes.c_double(), ctypes.c_double()
+    lib.lso_rho_map_grad(_ptr(cM), cM.size, float(s), float(gamma), _ptr(g), ctypes.byref(gs),
+                         ctypes.byref(gg))
+    return gs.value, gg.value
 
 
 def version() -> str:

@@ -494,4 +494,37 @@ void lso_symmetrise(const double *E, int32_t N, double *D)
             D[(int64_t)a * N + b] = (a == b) ? 0.0 : E[(int64_t)a * N + b] + E[(int64_t)b * N + a];
 }
 
+/* Recombination probabilities from map distances (eq. rho):
+ *   rho_l = 1 - exp(-s m_l^gamma),  m_l = cM_l / 100,
+ * the distance in Morgans (the paper's CalcRho takes centimorgans), with s
+ * the scalar multiple N_e and gamma the power; evaluated with expm1. */
+void lso_calc_rho(const double *cM, int32_t n, double s, double gamma, double *rho)
+{
+    for (int l = 0; l < n; ++l) {
+        double m = cM[l] / 100.0;
+        rho[l] = -expm1(-s * pow(m, gamma));
+    }
+}
+
+/* Chain rule from d/d rho_l to the map parameters. With x_l = s m_l^gamma:
+ *   d rho_l / d s     = m_l^gamma exp(-x_l)
+ *   d rho_l / d gamma = s m_l^gamma log(m_l) exp(-x_l)   (0 where m_l = 0)
+ * grad_s = sum_l grad_rho[l] d rho_l / d s, grad_gamma likewise. */
+void lso_rho_map_grad(const double *cM, int32_t n, double s, double gamma,
+                      const double *grad_rho, double *grad_s, double *grad_gamma)
+{
+    double gs = 0.0, gg = 0.0;
+    for (int l = 0; l < n; ++l) {
+        double m = cM[l] / 100.0;
+        if (!(m > 0.0))
+            continue;
+        double mg = pow(m, gamma);
+        double e = exp(-s * mg);
+        gs += grad_rho[l] * mg * e;
+        gg += grad_rho[l] * s * mg * log(m) * e;
+    }
+    *grad_s = gs;
+    *grad_gamma = gg;
+}
+
 const char *lso_version(void) { return "ls_oracle 1.0 (FP64 reference, test infrastructure)"; }

@@ -169,3 +169,38 @@ def rho1_closed_form(h01, mu, i):
     w = th / (N - 1)
     s = w.sum(axis=1)
     return float(np.log(s).sum()), w / s[:, None]
+
+
+def rho_map_checks(calc_rho, rho_map_grad, printed_pairs) -> bool:
+    """Checks of the recombination map (eq. rho) and its chain rule that do
+    not reuse the code under test: the paper's printed CalcRho values (with
+    s = gamma = 1, reading the centimorgan argument as m = cM / 100 Morgans),
+    the gamma = 1 closed form 1 - exp(-s m) at distances where it has no
+    cancellation, the limits s = 0, m = 0 and m large, and central
+    differences of f(s, gamma) = sum_l g_l rho_l(s, gamma)."""
+    ok = True
+    for m, printed in printed_pairs:
+        got = calc_rho(np.array([100.0 * float(m)]), 1.0, 1.0)[0]
+        ok &= abs(got - float(printed)) <= 1e-13 * float(printed)
+    cM = np.array([0.5, 3.0, 10.0, 40.0, 150.0])
+    ok &= bool(np.allclose(calc_rho(cM, 0.7, 1.0), 1.0 - np.exp(-0.7 * cM / 100.0),
+                           rtol=1e-14, atol=0.0))
+    ok &= bool(np.all(calc_rho(cM, 0.0, 1.3) == 0.0))
+    ok &= calc_rho(np.array([0.0]), 2.0, 0.5)[0] == 0.0
+    ok &= calc_rho(np.array([1e6]), 1.0, 1.0)[0] == 1.0
+    rng = np.random.default_rng(5)
+    cM = rng.exponential(2.0, 40)
+    cM[::7] = 0.0
+    g = rng.normal(size=40)
+    s, ga = 1.7, 0.8
+    gs, gg = rho_map_grad(cM, s, ga, g)
+
+    def f(s_, g_):
+        return float(np.dot(g, calc_rho(cM, s_, g_)))
+
+    hs, hg = 1e-6 * s, 1e-6 * ga
+    fds = (f(s + hs, ga) - f(s - hs, ga)) / (2 * hs)
+    fdg = (f(s, ga + hg) - f(s, ga - hg)) / (2 * hg)
+    ok &= abs(gs - fds) <= 1e-7 * abs(fds)
+    ok &= abs(gg - fdg) <= 1e-7 * abs(fdg)
+    return bool(ok)

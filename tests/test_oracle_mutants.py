@@ -18,7 +18,7 @@ import pytest
 import oracle
 from lsinputs import pack_haplotypes
 
-from _pins import enumerate_exact
+from _pins import enumerate_exact, rho_map_checks
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "ls_oracle.c")
 
@@ -40,6 +40,24 @@ MUTANTS = {
     "distance_not_halved": ("return -log(q) / 2.0;", "return -log(q);"),
     "posterior_not_normalised": ("p[j] = alpha[j] * beta[j] / Z;", "p[j] = alpha[j] * beta[j];"),
 }
+
+
+# mistakes in the recombination map (eq. rho) and its chain rule, caught by
+# the map's own pins
+RHO_MAP_MUTANTS = {
+    "calc_rho_no_morgan_conversion": ("double m = cM[l] / 100.0;\n        rho[l]",
+                                      "double m = cM[l];\n        rho[l]"),
+    "rho_map_grad_drops_log": ("s * mg * log(m) * e", "s * mg * e"),
+    "rho_map_grad_s_sign": ("gs += grad_rho[l] * mg * e;", "gs -= grad_rho[l] * mg * e;"),
+}
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_printed_values.json")
+
+
+def _rho_map_pins_pass(lib) -> bool:
+    import json
+    pairs = json.load(open(GOLDEN))["calc_rho"]["pairs"]
+    return rho_map_checks(lambda c, s, g: oracle.calc_rho(c, s, g, lib=lib),
+                          lambda c, s, g, gr: oracle.rho_map_grad(c, s, g, gr, lib=lib), pairs)
 
 
 def _build_mutant(tmp_path, name, find, repl):
@@ -89,6 +107,14 @@ def test_unmutated_copy_passes(tmp_path):
     lib = _build_mutant(tmp_path, "identity", "LSO_EPS 2.220446049250313080847e-16",
                         "LSO_EPS 2.220446049250313080847e-16")
     assert _pins_pass(lib)
+    assert _rho_map_pins_pass(lib)
+
+
+@pytest.mark.parametrize("name", sorted(RHO_MAP_MUTANTS))
+def test_rho_map_pins_catch_mutant(tmp_path, name):
+    find, repl = RHO_MAP_MUTANTS[name]
+    lib = _build_mutant(tmp_path, name, find, repl)
+    assert not _rho_map_pins_pass(lib), f"pins did not catch mutant {name}"
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))

@@ -17,7 +17,7 @@ from lsinputs import (evenly_spaced_targets, make_inputs, pack_haplotypes, packe
                       rho_from_spacings, unpack_haplotypes)
 
 from _pins import (enumerate_exact, logdomain_fb, raw_forward, rho0_closed_form,
-                   rho0_closed_form_grad, rho1_closed_form)
+                   rho0_closed_form_grad, rho1_closed_form, rho_map_checks)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_printed_values.json")
 
@@ -300,6 +300,12 @@ def test_paper_calc_rho_values():
         # printed to 15 digits from a map difference that is itself rounded;
         # 1 - exp(-m) differs from m by m/2 relative (~1e-8), far above this
         assert abs(got - float(printed)) <= 1e-13 * float(printed)
+
+
+def test_oracle_recombination_map():
+    """The oracle's CalcRho (eq. rho) and its chain rule to (s, gamma)."""
+    g = json.load(open(GOLDEN))["calc_rho"]
+    assert rho_map_checks(oracle.calc_rho, oracle.rho_map_grad, g["pairs"])
 
 
 def test_oracle_epsilon_matches_paper():
