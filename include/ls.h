@@ -216,6 +216,29 @@ ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R
                          ls_precision prec, double *loglik, double *pac, double *grad_rho,
                          double *grad_mu, void *workspace, size_t ws_bytes, void *stream);
 
+/* Recombination probabilities from a genetic map (eq. rho, section 2.1;
+ * the paper's CalcRho, section 3.4):
+ *   rho[l] = 1 - exp(-s (cM[l] / 100)^gamma),  l = 0 .. n-1,
+ * where cM[l] is the map distance between variants l and l+1 in
+ * centimorgans (cM / 100 is the distance in Morgans of eq. rho), s the
+ * scalar multiple N_e and gamma the power; evaluated with expm1.
+ * cM, rho: device, [n] double (n = L - 1 for a model's rho); cM >= 0.
+ * Errors: LS_ERR_ARG (n < 0, null pointers, s < 0, gamma <= 0, or a
+ * non-finite s or gamma), LS_ERR_DEVICE. */
+ls_status ls_calc_rho(const double *cM, int32_t n, double s, double gamma, double *rho,
+                      void *stream);
+
+/* Chain rule from a gradient w.r.t. rho (such as ls_loglik_grad's
+ * grad_rho) to the map parameters of ls_calc_rho: with x_l = s m_l^gamma,
+ * m_l = cM[l] / 100,
+ *   grad_s_gamma[0] = sum_l grad_rho[l] m_l^gamma exp(-x_l)
+ *   grad_s_gamma[1] = sum_l grad_rho[l] s m_l^gamma log(m_l) exp(-x_l)
+ * (terms with m_l = 0 are 0), summed in a fixed order.
+ * cM, grad_rho: device, [n] double; grad_s_gamma: device, [2] double.
+ * Errors: as ls_calc_rho. */
+ls_status ls_rho_map_grad(const double *cM, int32_t n, double s, double gamma,
+                          const double *grad_rho, double *grad_s_gamma, void *stream);
+
 /* Workspace bytes ls_loglik_grad needs (0 on bad arguments). */
 size_t ls_loglik_grad_workspace_bytes(const ls_model *m, int32_t R, ls_precision prec);
 

@@ -30,7 +30,7 @@ EXPORTED = [
     "ls_model_workspace_bytes", "ls_model_init", "ls_table_init", "ls_table_copy",
     "ls_forward", "ls_backward", "ls_posterior_distance", "ls_distance_symmetrise",
     "ls_loglik_grad", "ls_loglik_grad_workspace_bytes", "ls_status_check",
-    "ls_kernel_shape", "ls_status_string", "ls_version",
+    "ls_kernel_shape", "ls_status_string", "ls_version", "ls_calc_rho", "ls_rho_map_grad",
 ]
 
 
@@ -112,6 +112,8 @@ def load():
                                            ctypes.POINTER(I32)]),
         "ls_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "ls_version": (ctypes.c_char_p, []),
+        "ls_calc_rho": (ctypes.c_int, [P, I32, D, D, P, P]),
+        "ls_rho_map_grad": (ctypes.c_int, [P, I32, D, D, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

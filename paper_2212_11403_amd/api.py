@@ -186,6 +186,34 @@ def kernel_shape(N: int, prec="fp32"):
     return a.value, b.value
 
 
+def _f64_device(x) -> torch.Tensor:
+    t = torch.as_tensor(x, dtype=torch.float64)
+    return (t if t.is_cuda else t.to("cuda")).contiguous()
+
+
+def calc_rho(cM, s: float = 1.0, gamma: float = 1.0, stream=None) -> torch.Tensor:
+    """rho = 1 - exp(-s (cM / 100)^gamma) (eq. rho; cM in centimorgans, one
+    value per interval between consecutive variants) on the device."""
+    c = _f64_device(cM)
+    rho = torch.empty_like(c)
+    check(_lib.load().ls_calc_rho(_p(c), int(c.numel()), float(s), float(gamma), _p(rho),
+                                  _stream(stream)), "ls_calc_rho")
+    return rho
+
+
+def rho_map_grad(cM, s: float, gamma: float, grad_rho, stream=None) -> torch.Tensor:
+    """(d/ds, d/dgamma) from a gradient w.r.t. rho = calc_rho(cM, s, gamma):
+    a device float64 tensor of 2."""
+    c = _f64_device(cM)
+    g = _f64_device(grad_rho)
+    if g.numel() != c.numel():
+        raise ValueError("grad_rho and cM differ in length")
+    out = torch.empty(2, dtype=torch.float64, device=c.device)
+    check(_lib.load().ls_rho_map_grad(_p(c), int(c.numel()), float(s), float(gamma), _p(g),
+                                      _p(out), _stream(stream)), "ls_rho_map_grad")
+    return out
+
+
 def loglik_grad(model: Model, recipients=None, prec="fp32", grad: bool = True, stream=None):
     """Per-recipient log-likelihood, their sum (PAC) and optionally the
     gradient of the sum w.r.t. rho (L-1) and mu. Returns a dict of device

@@ -503,6 +503,25 @@ ls_status ls_distance_symmetrise(const void *E, void *D, int32_t N, int32_t T,
     return dev(lsk::launch_symmetrise(E, D, N, T, prec == LS_FP64, as_stream(stream)));
 }
 
+ls_status ls_calc_rho(const double *cM, int32_t n, double s, double gamma, double *rho,
+                      void *stream) {
+    clear_stale_hip_error();
+    if (n < 0 || (n > 0 && (!cM || !rho)) || !std::isfinite(s) || !std::isfinite(gamma) ||
+        s < 0.0 || gamma <= 0.0)
+        return LS_ERR_ARG;
+    return dev(lsk::launch_calc_rho(cM, n, s, gamma, rho, as_stream(stream)));
+}
+
+ls_status ls_rho_map_grad(const double *cM, int32_t n, double s, double gamma,
+                          const double *grad_rho, double *grad_s_gamma, void *stream) {
+    clear_stale_hip_error();
+    if (n < 0 || (n > 0 && (!cM || !grad_rho)) || !grad_s_gamma || !std::isfinite(s) ||
+        !std::isfinite(gamma) || s < 0.0 || gamma <= 0.0)
+        return LS_ERR_ARG;
+    return dev(lsk::launch_rho_map_grad(cM, n, s, gamma, grad_rho, grad_s_gamma,
+                                        as_stream(stream)));
+}
+
 size_t ls_loglik_grad_workspace_bytes(const ls_model *m, int32_t R, ls_precision prec) {
     if (check_model(m) != LS_OK || R < 1 || !valid_prec(prec)) return 0;
     return lsk::grad_workspace_bytes(m->N, m->L, R, (int)prec, nullptr);

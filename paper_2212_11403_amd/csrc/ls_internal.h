@@ -180,6 +180,11 @@ hipError_t launch_coef_tables(const double *rho, int32_t L, const CoefScalars &c
 hipError_t launch_repack(const uint32_t *H, int64_t stride_words, int32_t N, int32_t L,
                          uint64_t *Hr, int64_t hr_stride, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
+// Recombination map (eq. rho) and its chain rule (ls_misc.hip)
+hipError_t launch_calc_rho(const double *cM, int32_t n, double s, double gamma, double *rho,
+                           hipStream_t st);
+hipError_t launch_rho_map_grad(const double *cM, int32_t n, double s, double gamma,
+                               const double *g, double *out, hipStream_t st);
 hipError_t launch_symmetrise(const void *E, void *D, int32_t N, int32_t T, int is_f64,
                              hipStream_t st);
 // Posterior and half distances for `rows` rows of length N: row q holds the

@@ -393,4 +393,66 @@ hipError_t launch_symmetrise(const void *E, void *D, int32_t N, int32_t T, int i
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Recombination map (eq. rho): rho_l = 1 - exp(-s m_l^gamma) with m_l =
+// cM_l / 100 the distance in Morgans (the argument is in centimorgans, as
+// the paper's CalcRho takes it), evaluated with expm1.
+__global__ void calc_rho_kernel(const double *__restrict__ cM, int32_t n, double s, double gamma,
+                                double *__restrict__ rho) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double m = cM[i] / 100.0;
+        rho[i] = -expm1(-s * pow(m, gamma));
+    }
+}
+
+hipError_t launch_calc_rho(const double *cM, int32_t n, double s, double gamma, double *rho,
+                           hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(calc_rho_kernel, dim3(blocks), dim3(256), 0, st, cM, n, s, gamma, rho);
+    return hipGetLastError();
+}
+
+// Chain rule to the map parameters: with x_l = s m_l^gamma,
+//   d rho_l / d s = m_l^gamma e^{-x_l},  d rho_l / d gamma = s m_l^gamma log(m_l) e^{-x_l}
+// (0 where m_l = 0); out = {sum_l g_l d rho_l / d s, sum_l g_l d rho_l / d gamma}.
+// One workgroup: per-thread strided sums in index order, then a fixed tree,
+// so the result does not depend on scheduling.
+__global__ void __launch_bounds__(256)
+rho_map_grad_kernel(const double *__restrict__ cM, int32_t n, double s, double gamma,
+                    const double *__restrict__ g, double *__restrict__ out) {
+    __shared__ double ps[256], pg[256];
+    double as = 0.0, ag = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const double m = cM[i] / 100.0;
+        if (m > 0.0) {
+            const double mg = pow(m, gamma);
+            const double e = exp(-s * mg);
+            as += g[i] * mg * e;
+            ag += g[i] * s * mg * log(m) * e;
+        }
+    }
+    ps[threadIdx.x] = as;
+    pg[threadIdx.x] = ag;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            ps[threadIdx.x] += ps[threadIdx.x + h];
+            pg[threadIdx.x] += pg[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = ps[0];
+        out[1] = pg[0];
+    }
+}
+
+hipError_t launch_rho_map_grad(const double *cM, int32_t n, double s, double gamma,
+                               const double *g, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(rho_map_grad_kernel, dim3(1), dim3(256), 0, st, cM, n, s, gamma, g, out);
+    return hipGetLastError();
+}
+
 }  // namespace lsk

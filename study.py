@@ -122,6 +122,21 @@ def study_c4(args):
                      "hbm_frac": hbm / (ms / 1e3) / HBM_PEAK,
                      "pac": float(g["pac"].item())}
         log(f"{prec}: gradient {ms:.1f} ms, log-likelihood only {ms_ll:.1f} ms")
+    # the recombination map (eq. rho) and its chain rule to (s, gamma) over
+    # the L - 1 intervals: map distances that give this rho at s = gamma = 1
+    cM = torch.tensor(-100.0 * np.log1p(-rho), dtype=torch.float64, device="cuda")
+    gr_dev = res["fp32"]["grad_rho"].contiguous()
+    ls.calc_rho(cM, 1.0, 1.0)
+    ls.rho_map_grad(cM, 1.0, 1.0, gr_dev)
+    torch.cuda.synchronize()
+    e0, e1 = events()
+    e0.record()
+    for _ in range(10):
+        ls.calc_rho(cM, 1.3, 0.9)
+        ls.rho_map_grad(cM, 1.3, 0.9, gr_dev)
+    e1.record()
+    torch.cuda.synchronize()
+    out["rho_map_and_chain_rule_ms"] = e0.elapsed_time(e1) / 10
     g32, g64 = res["fp32"], res["fp64"]
     gr32 = g32["grad_rho"].cpu().numpy()
     gr64 = g64["grad_rho"].cpu().numpy()
