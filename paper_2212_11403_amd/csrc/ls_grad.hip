@@ -115,7 +115,7 @@ sum_rows_kernel(const double *__restrict__ grow, int32_t R, int32_t rows, double
 // Whole gradient: a forward sweep with checkpoints every `seg` variants (its
 // table also gives log P per recipient), then, segment by segment from the
 // last, a forward recompute of the segment from its checkpoint (sweep kernel
-// with a snapshot at every variant) followed by the adjoint pass above.
+// in its keep-alpha mode) followed by the adjoint pass (ls_grad_kernel.h).
 hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, double *pac,
                        double *grad_rho, double *grad_mu, hipStream_t st) {
     const GradLayout &Ly = ga.lay;

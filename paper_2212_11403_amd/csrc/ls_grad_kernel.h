@@ -19,7 +19,8 @@ namespace lsk {
 // Sy = sum_j y^{l+1}_j (all reductions over the donor column),
 //   d log P / d rho_l = (pi Sa Sy - d) / ((1 - rho_l) d + rho_l pi Sa Sy)
 // (the exact score of the transition; homogeneous in alpha and y, so any
-// scaling of the stored vectors cancels, the FP32 emission unit included), and, with beta^l = c y^{l+1} + b,
+// scaling of the stored vectors cancels, the FP32 emission unit included),
+// and, with beta^l = c y^{l+1} + b,
 //   M_l = sum_{j mismatching at l} alpha^l_j beta^l_j / sum_j alpha^l_j beta^l_j
 //   d log P / d mu += M_l / mu - (1 - M_l) / (1 - mu).
 // Per-variant rho terms go to grow[l][r]; the mu term accumulates in gmu[r].

@@ -121,7 +121,7 @@ __host__ __device__ constexpr int sweep_waves_per_simd(int nslot, int vgpr_per_s
 }
 
 // Slot count whose sweep_waves_per_simd budget the sweep kernel is compiled
-// for. Keeping alpha at every variant (the gradient's recompute) holds more
+// for. The keep-alpha mode (the gradient's recompute) holds more
 // registers: in FP32 about two per slot (measured).
 __host__ __device__ constexpr int sweep_budget_slots(int nslot, int vgpr_per_slot, bool every) {
     if (!every) return nslot;
