@@ -45,6 +45,9 @@ def bind(path: str):
     lib.lso_pass.argtypes = [P, i64, i32, i32, P, f64, P, i32, P, i32,
                              P, P, P, P, P, P, P, P, P, i32]
     lib.lso_pass.restype = ctypes.c_int
+    lib.lso_pass_v.argtypes = [P, i64, i32, i32, P, P, P, i32, P, i32,
+                               P, P, P, P, P, P, P, P, P, i32]
+    lib.lso_pass_v.restype = ctypes.c_int
     lib.lso_gradient.argtypes = [P, i64, i32, i32, P, f64, P, i32, P, P, P, P, i32]
     lib.lso_gradient.restype = ctypes.c_int
     lib.lso_symmetrise.argtypes = [P, i32, P]
@@ -74,7 +77,8 @@ def default_threads() -> int:
 
 
 def run_pass(H, N, L, rho, mu, recipients, targets=(), want=("P", "E"), nthreads=None, lib=None):
-    """Forward/backward pass for each recipient.
+    """Forward/backward pass for each recipient. ``mu`` is a scalar or a
+    per-variant array of L values.
 
     Returns a dict with ``llf``/``llb`` (forward and backward log-likelihood,
     shape [R]) and, for each name in ``want`` among A (alpha), B (beta), P
@@ -96,10 +100,20 @@ def run_pass(H, N, L, rho, mu, recipients, targets=(), want=("P", "E"), nthreads
     out["llf"] = np.empty(R)
     out["llb"] = np.empty(R)
     out["status"] = np.zeros(R, dtype=np.int32)
-    rc = lib.lso_pass(_ptr(H), H.shape[1], N, L, _ptr(rho), float(mu), _ptr(rec), R,
-                      _ptr(tg), T, _ptr(out["A"]), _ptr(out["B"]), _ptr(out["P"]),
-                      _ptr(out["E"]), _ptr(out["logF"]), _ptr(out["logG"]), _ptr(out["llf"]),
-                      _ptr(out["llb"]), _ptr(out["status"]), nthreads or default_threads())
+    if np.ndim(mu) == 1:
+        muv = np.ascontiguousarray(mu, dtype=np.float64)
+        if muv.size != L:
+            raise ValueError("a per-variant mu needs L values")
+        rc = lib.lso_pass_v(_ptr(H), H.shape[1], N, L, _ptr(rho), _ptr(muv), _ptr(rec), R,
+                            _ptr(tg), T, _ptr(out["A"]), _ptr(out["B"]), _ptr(out["P"]),
+                            _ptr(out["E"]), _ptr(out["logF"]), _ptr(out["logG"]),
+                            _ptr(out["llf"]), _ptr(out["llb"]), _ptr(out["status"]),
+                            nthreads or default_threads())
+    else:
+        rc = lib.lso_pass(_ptr(H), H.shape[1], N, L, _ptr(rho), float(mu), _ptr(rec), R,
+                          _ptr(tg), T, _ptr(out["A"]), _ptr(out["B"]), _ptr(out["P"]),
+                          _ptr(out["E"]), _ptr(out["logF"]), _ptr(out["logG"]), _ptr(out["llf"]),
+                          _ptr(out["llb"]), _ptr(out["status"]), nthreads or default_threads())
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
     return {k: v for k, v in out.items() if v is not None}

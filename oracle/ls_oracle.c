@@ -56,6 +56,7 @@ typedef struct {
     int32_t N, L;
     const double *rho; /* [L-1] */
     double mu;
+    const double *mu_vec; /* [L] per-variant mu^l, or NULL: mu at every variant */
 } lso_model;
 
 /* allele of haplotype j at variant l: bit (j mod 32) of word floor(j/32) */
@@ -64,10 +65,18 @@ static int allele(const lso_model *m, int l, int j)
     return (int)((m->H[(int64_t)l * m->stride + (j >> 5)] >> (j & 31)) & 1u);
 }
 
+/* mutation probability at variant l (the paper's mu may be a vector of
+ * length L, section 3.4) */
+static double mu_at(const lso_model *m, int l)
+{
+    return m->mu_vec ? m->mu_vec[l] : m->mu;
+}
+
 static double theta(const lso_model *m, int l, int j, int i)
 {
     int Hm = allele(m, l, j) ^ allele(m, l, i);
-    return (double)(1 - Hm) * (1.0 - 2.0 * m->mu) + m->mu;
+    double mu = mu_at(m, l);
+    return (double)(1 - Hm) * (1.0 - 2.0 * mu) + mu;
 }
 
 static double prior(const lso_model *m, int j, int i)
@@ -269,7 +278,7 @@ static int recipient_gradient(const lso_model *m, int i, double *grad_rho, doubl
             if (j == i)
                 continue;
             int Hm = allele(m, l, j) ^ allele(m, l, i);
-            gmu += Hm ? p[j] / m->mu : -p[j] / (1.0 - m->mu);
+            gmu += Hm ? p[j] / mu_at(m, l) : -p[j] / (1.0 - mu_at(m, l));
         }
         if (l == 0)
             break;
@@ -428,12 +437,41 @@ static int check_model(const lso_model *m)
 /* Forward/backward/posterior/distance pass for recipients recips[0..R-1].
  * Target outputs are [T][R][N]; logF/logG are [T][R]; llf/llb/status [R].
  * Any output pointer may be NULL. Returns 0, or 1 on a bad argument. */
+static int pass_model(const lso_model *mp, const int32_t *recips, int32_t R,
+                      const int32_t *targets, int32_t T, double *A, double *B, double *P,
+                      double *E, double *logF, double *logG, double *llf, double *llb,
+                      int32_t *status, int32_t nthreads);
+
 int lso_pass(const uint32_t *H, int64_t stride, int32_t N, int32_t L, const double *rho,
              double mu, const int32_t *recips, int32_t R, const int32_t *targets, int32_t T,
              double *A, double *B, double *P, double *E, double *logF, double *logG,
              double *llf, double *llb, int32_t *status, int32_t nthreads)
 {
-    lso_model m = {H, stride, N, L, rho, mu};
+    lso_model m = {H, stride, N, L, rho, mu, NULL};
+    return pass_model(&m, recips, R, targets, T, A, B, P, E, logF, logG, llf, llb, status,
+                      nthreads);
+}
+
+/* As lso_pass with a per-variant mutation probability mu_vec[0..L-1]. */
+int lso_pass_v(const uint32_t *H, int64_t stride, int32_t N, int32_t L, const double *rho,
+               const double *mu_vec, const int32_t *recips, int32_t R, const int32_t *targets,
+               int32_t T, double *A, double *B, double *P, double *E, double *logF,
+               double *logG, double *llf, double *llb, int32_t *status, int32_t nthreads)
+{
+    if (!mu_vec)
+        return 1;
+    lso_model m = {H, stride, N, L, rho, 0.0, mu_vec};
+    return pass_model(&m, recips, R, targets, T, A, B, P, E, logF, logG, llf, llb, status,
+                      nthreads);
+}
+
+static int pass_model(const lso_model *mp, const int32_t *recips, int32_t R,
+                      const int32_t *targets, int32_t T, double *A, double *B, double *P,
+                      double *E, double *logF, double *logG, double *llf, double *llb,
+                      int32_t *status, int32_t nthreads)
+{
+    const lso_model m = *mp;
+    const int32_t L = m.L, N = m.N;
     if (check_model(&m) || R < 0 || (R > 0 && !recips) || T < 0 || (T > 0 && !targets))
         return 1;
     for (int k = 0; k < T; ++k)
@@ -466,7 +504,7 @@ int lso_gradient(const uint32_t *H, int64_t stride, int32_t N, int32_t L, const 
                  double mu, const int32_t *recips, int32_t R, double *grad_rho_rows,
                  double *grad_mu, double *loglik, int32_t *status, int32_t nthreads)
 {
-    lso_model m = {H, stride, N, L, rho, mu};
+    lso_model m = {H, stride, N, L, rho, mu, NULL};
     if (check_model(&m) || R < 0 || (R > 0 && (!recips || !grad_mu || !loglik)) ||
         (L > 1 && !grad_rho_rows))
         return 1;

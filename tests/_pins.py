@@ -31,16 +31,19 @@ def enumerate_exact(h, rho, mu, i):
     """Exact P(h_i | h_-i), posterior marginals p[l][j] and the derivatives
     d log P / d rho_l (length L-1) and d log P / d mu, by summing over all
     (N-1)^L copying paths. ``h`` is an L x N nested list of 0/1; ``rho`` a list
-    of L-1 Fractions; ``mu`` a Fraction."""
+    of L-1 Fractions; ``mu`` a Fraction, or a list of L Fractions (one per
+    variant), in which case ``dlogP_dmu_l`` holds the derivative with respect
+    to each."""
     L, N = len(h), len(h[0])
+    mus = list(mu) if isinstance(mu, (list, tuple)) else [mu] * L
     donors = [j for j in range(N) if j != i]
     pi = Fraction(1, N - 1)
     P = Fraction(0)
     marg = [[Fraction(0)] * N for _ in range(L)]
     dP_drho = [Fraction(0)] * (L - 1)
-    dP_dmu = Fraction(0)
+    dP_dmu = [Fraction(0)] * L
     for path in itertools.product(donors, repeat=L):
-        em = [_theta_exact(h, l, path[l], i, mu) for l in range(L)]
+        em = [_theta_exact(h, l, path[l], i, mus[l]) for l in range(L)]
         tr = [rho[l] * pi + (1 - rho[l]) * (1 if path[l] == path[l + 1] else 0)
               for l in range(L - 1)]
         prob = pi
@@ -70,9 +73,10 @@ def enumerate_exact(h, rho, mu, i):
                     rest *= e
             for t in tr:
                 rest *= t
-            dP_dmu += rest * d
+            dP_dmu[l] += rest * d
     post = [[marg[l][j] / P for j in range(N)] for l in range(L)]
-    return dict(P=P, post=post, dlogP_drho=[d / P for d in dP_drho], dlogP_dmu=dP_dmu / P)
+    return dict(P=P, post=post, dlogP_drho=[d / P for d in dP_drho],
+                dlogP_dmu=sum(dP_dmu) / P, dlogP_dmu_l=[d / P for d in dP_dmu])
 
 
 def _logsumexp(a, axis=None):

@@ -26,7 +26,7 @@ MUTANTS = {
     "forward_drops_normalisation": ("(1.0 - r) * prev[j] / S", "(1.0 - r) * prev[j]"),
     "forward_rho_index": ("double r = m->rho[l - 1];\n    for (int j = 0; j < m->N; ++j) {\n        if (j == i) {\n            next[j] = 0.0;",
                           "double r = m->rho[l > 1 ? l - 2 : 0];\n    for (int j = 0; j < m->N; ++j) {\n        if (j == i) {\n            next[j] = 0.0;"),
-    "emission_swapped": ("(double)(1 - Hm) * (1.0 - 2.0 * m->mu)", "(double)(Hm) * (1.0 - 2.0 * m->mu)"),
+    "emission_swapped": ("(double)(1 - Hm) * (1.0 - 2.0 * mu) + mu", "(double)(Hm) * (1.0 - 2.0 * mu) + mu"),
     "prior_keeps_self": ("return j == i ? 0.0 : 1.0 / (double)(m->N - 1);",
                          "return 1.0 / (double)(m->N - 1);"),
     "backward_theta_index": ("cur[j] = (1.0 - r) * next[j] * theta(m, l + 1, j, i) / g + r;",
@@ -36,7 +36,7 @@ MUTANTS = {
     "grad_rho_sign": ("grad_rho[l - 1] = (Sg - a) /", "grad_rho[l - 1] = (a - Sg) /"),
     "grad_rho_uses_wrong_alpha": ("const double *al = alpha + (int64_t)(l - 1) * N;",
                                   "const double *al = alpha + (int64_t)(l) * N;"),
-    "grad_mu_sign": ("-p[j] / (1.0 - m->mu);", "p[j] / (1.0 - m->mu);"),
+    "grad_mu_sign": ("-p[j] / (1.0 - mu_at(m, l));", "p[j] / (1.0 - mu_at(m, l));"),
     "distance_not_halved": ("return -log(q) / 2.0;", "return -log(q);"),
     "posterior_not_normalised": ("p[j] = alpha[j] * beta[j] / Z;", "p[j] = alpha[j] * beta[j];"),
 }

@@ -69,6 +69,38 @@ def test_oracle_matches_exact_enumeration(L, N, seed, mu, rnum):
         assert abs(grad["grad_mu"][i] - float(ex["dlogP_dmu"])) <= 1e-10 * abs(float(ex["dlogP_dmu"])) + 1e-10
 
 
+@pytest.mark.parametrize("L,N,seed,mnum,rnum", [
+    (5, 4, 6, [1, 3, 2, 8, 1], [3, 17, 1, 29]),
+    (6, 3, 7, [4, 1, 1, 16, 2, 5], [5, 0, 31, 12, 32]),
+])
+def test_oracle_per_variant_mu_matches_enumeration(L, N, seed, mnum, rnum):
+    """A mutation probability per variant (the paper's mu may be a vector of
+    length L, section 3.4): posteriors and likelihoods by enumeration."""
+    h01 = _rand_h(L, N, seed)
+    rho = [Fraction(k, 32) for k in rnum]
+    mu = [Fraction(k, 32) for k in mnum]
+    res = _run(h01, [float(r) for r in rho], np.array([float(m) for m in mu]),
+               np.arange(N, dtype=np.int32), np.arange(L, dtype=np.int32))
+    for i in range(N):
+        ex = enumerate_exact(h01.tolist(), rho, mu, i)
+        logP = np.log(float(ex["P"]))
+        assert abs(res["llf"][i] - logP) <= 1e-13 * abs(logP) + 1e-14
+        assert abs(res["llb"][i] - logP) <= 1e-13 * abs(logP) + 1e-14
+        post = np.array([[float(x) for x in row] for row in ex["post"]])
+        np.testing.assert_allclose(res["P"][:, i, :], post, rtol=1e-12, atol=1e-15)
+
+
+def test_oracle_constant_mu_vector_equals_scalar():
+    L, N = 40, 9
+    h01 = _rand_h(L, N, 12)
+    rho = rho_from_spacings(np.random.default_rng(12).exponential(0.05, L - 1))
+    rec, tg = np.arange(N, dtype=np.int32), np.array([3, 20, 39], np.int32)
+    a = _run(h01, rho, 0.03, rec, tg)
+    b = _run(h01, rho, np.full(L, 0.03), rec, tg)
+    for k in ("P", "E", "llf", "llb", "logF", "logG"):
+        assert np.array_equal(a[k], b[k]), k
+
+
 def test_distance_definition_on_enumerated_posteriors():
     """eq. distmat applied to exact posteriors equals the oracle's D."""
     L, N = 5, 4
