@@ -50,7 +50,8 @@ typedef enum {
     LS_ERR_SHAPE = 2,       /* sizes inconsistent with each other */
     LS_ERR_STATE = 3,       /* table at the wrong variant or direction, or
                                built with another model (hash mismatch) */
-    LS_ERR_UNSUPPORTED = 4, /* N too large for this precision on one GPU */
+    LS_ERR_UNSUPPORTED = 4, /* N too large for this precision on one GPU, or a
+                               per-variant mu where it is not supported */
     LS_ERR_DEVICE = 5,      /* the HIP runtime reported an error */
     LS_ERR_WORKSPACE = 6,   /* workspace missing or too small */
     LS_WARN_NONFINITE = 16  /* returned by ls_status_check only */
@@ -89,16 +90,24 @@ typedef struct {
     const double *rho;    /* device, [L-1], each in [0, 1]; may be NULL if L == 1 */
     double mu;            /* in [0, 1] */
     /* set by ls_model_init */
-    uint64_t hash;        /* hash of (N, L, rho, mu); tables remember it */
+    uint64_t hash;        /* hash of (N, L, rho, mu, mu_vec); tables remember it */
     const uint64_t *Hr;   /* device: internal row layout in the workspace */
     int64_t hr_stride;    /* 64-bit words per internal row */
     int32_t nf;           /* number of full 64-haplotype words: floor(N/64) */
     int32_t reserved;
+    /* optional, set by the caller before ls_model_init: */
+    const double *mu_vec; /* device, [L] mutation probability per variant (the
+                             paper's vector mu, section 3.4), each in [0, 1],
+                             or NULL: mu at every variant. Used by decoding and
+                             the log-likelihood in LS_FP64 and LS_FP32; the
+                             FP16-stored tables and the gradient return
+                             LS_ERR_UNSUPPORTED for such a model. */
 } ls_model;
 
 /* Device bytes of the workspace ls_model_init lays the internal haplotype
- * rows (about 2 N L / 8 bytes) and the per-variant FP32 transition
- * coefficients of the sweeps (32 L bytes) into. */
+ * rows (about 2 N L / 8 bytes), the per-variant FP32 transition
+ * coefficients of the sweeps (32 L bytes) and the per-variant emission
+ * tables for a vector mu (32 L + 8 bytes) into. */
 size_t ls_model_workspace_bytes(int32_t N, int32_t L);
 
 /* Validates the inputs, computes the hash and builds the internal rows in

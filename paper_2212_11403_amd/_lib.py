@@ -47,6 +47,7 @@ class LsModel(ctypes.Structure):
         ("hr_stride", ctypes.c_int64),
         ("nf", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("mu_vec", ctypes.c_void_p),
     ]
 
 

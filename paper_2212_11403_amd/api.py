@@ -56,10 +56,11 @@ class Model:
     """Haplotypes and parameters on the device (cf. kalis Parameters).
 
     H: L x stride packed haplotypes (numpy uint32 or a device tensor).
-    rho: L-1 recombination probabilities; mu: mutation probability.
+    rho: L-1 recombination probabilities; mu: mutation probability, a scalar
+    or one value per variant (L values; section 3.4 allows either).
     """
 
-    def __init__(self, H, N: int, rho, mu: float, device="cuda", stream=None):
+    def __init__(self, H, N: int, rho, mu, device="cuda", stream=None):
         lib = _lib.load()
         dev = torch.device(device)
         if isinstance(H, np.ndarray):
@@ -79,7 +80,17 @@ class Model:
         self.c.N = int(N)
         self.c.L = L
         self.c.rho = self.rho.data_ptr() if self.rho.numel() else None
-        self.c.mu = float(mu)
+        self.mu_vec = None
+        if np.ndim(mu) == 0 and not (torch.is_tensor(mu) and mu.dim() > 0):
+            self.c.mu = float(mu)
+        else:
+            muv = mu.to(torch.float64) if torch.is_tensor(mu) else \
+                torch.as_tensor(np.asarray(mu, dtype=np.float64))
+            self.mu_vec = muv.to(dev).contiguous().reshape(-1)
+            if self.mu_vec.numel() != L:
+                raise ValueError("a per-variant mu must have L entries")
+            self.c.mu = 0.0
+            self.c.mu_vec = self.mu_vec.data_ptr()
         nbytes = lib.ls_model_workspace_bytes(int(N), L)
         if nbytes == 0:
             raise ValueError("invalid N or L")
@@ -97,8 +108,9 @@ class Model:
         return self.c.L
 
     @property
-    def mu(self) -> float:
-        return self.c.mu
+    def mu(self):
+        """The scalar mu, or the device tensor of per-variant values."""
+        return self.c.mu if self.mu_vec is None else self.mu_vec
 
 
 class Table:

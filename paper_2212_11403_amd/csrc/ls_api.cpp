@@ -41,6 +41,12 @@ size_t coef_offset_bytes(int32_t N, int32_t L) {
     return (rows + 255) / 256 * 256;
 }
 
+// Byte offset of the emission tables of a per-variant mu, after the
+// coefficient tables: [L][2] double, [L][2] float, [L+1] double.
+size_t emis_offset_bytes(int32_t N, int32_t L) {
+    return coef_offset_bytes(N, L) + (size_t)lsk::kCoefTables * 2 * (size_t)L * sizeof(float);
+}
+
 uint64_t fnv1a(uint64_t h, const void *data, size_t n) {
     const unsigned char *p = static_cast<const unsigned char *>(data);
     for (size_t i = 0; i < n; ++i) {
@@ -157,7 +163,8 @@ void fill_scalars(SweepArgs &a, const ls_model *m, int prec, int dir) {
     a.N = m->N;
     a.L = m->L;
     a.NF = m->N / 64;
-    const lsk::Emissions em = lsk::sweep_emissions(m->mu, prec != LS_FP64);
+    lsk::Emissions em = lsk::sweep_emissions(m->mu, prec != LS_FP64);
+    if (m->mu_vec) em.log_unit = 0.0;  // per variant, from the prefix table
     a.th_match = em.match;
     a.th_mis = em.mis;
     a.kappa = kappa;
@@ -180,6 +187,22 @@ const float *coef_table(const ls_model *m, int prec, int dir) {
     const int k = (prec == LS_FP32 ? lsk::kCoefF32Fwd : lsk::kCoefF16Fwd) + (dir ? 1 : 0);
     const char *base = reinterpret_cast<const char *>(m->Hr) + coef_offset_bytes(m->N, m->L);
     return reinterpret_cast<const float *>(base) + (size_t)k * 2 * (size_t)m->L;
+}
+
+// Per-variant mu: the emission pairs in the sweep's arithmetic type and, for
+// FP32 arithmetic, the log-unit prefix; null for a scalar mu.
+void emission_tables(const ls_model *m, int prec, SweepPtrs &p) {
+    p.emis = nullptr;
+    p.lu_prefix = nullptr;
+    if (!m->mu_vec) return;
+    const char *base = reinterpret_cast<const char *>(m->Hr) + emis_offset_bytes(m->N, m->L);
+    const size_t L = (size_t)m->L;
+    if (prec == LS_FP64) {
+        p.emis = base;
+    } else {
+        p.emis = base + 2 * L * sizeof(double);
+        p.lu_prefix = reinterpret_cast<const double *>(base + 2 * L * (sizeof(double) + sizeof(float)));
+    }
 }
 
 hipError_t launch_sweep(int prec, int dir, const SweepPtrs &p, const SweepArgs &a, Shape sh,
@@ -282,7 +305,8 @@ extern "C" {
 
 size_t ls_model_workspace_bytes(int32_t N, int32_t L) {
     if (N < 2 || L < 1) return 0;
-    return coef_offset_bytes(N, L) + (size_t)lsk::kCoefTables * 2 * (size_t)L * sizeof(float);
+    return emis_offset_bytes(N, L) + (size_t)L * (2 * sizeof(double) + 2 * sizeof(float)) +
+           (size_t)(L + 1) * sizeof(double);
 }
 
 ls_status ls_model_init(ls_model *m, void *workspace, size_t ws_bytes, void *stream) {
@@ -304,11 +328,21 @@ ls_status ls_model_init(ls_model *m, void *workspace, size_t ws_bytes, void *str
         for (double r : rho)
             if (!(r >= 0.0 && r <= 1.0)) return LS_ERR_ARG;
     }
+    std::vector<double> muv(m->mu_vec ? (size_t)m->L : 0);
+    if (!muv.empty()) {
+        hipError_t e = hipMemcpyAsync(muv.data(), m->mu_vec, muv.size() * sizeof(double),
+                                      hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return LS_ERR_DEVICE;
+        for (double x : muv)
+            if (!(x >= 0.0 && x <= 1.0)) return LS_ERR_ARG;
+    }
     uint64_t h = 1469598103934665603ull;
     h = fnv1a(h, &m->N, sizeof m->N);
     h = fnv1a(h, &m->L, sizeof m->L);
     h = fnv1a(h, &m->mu, sizeof m->mu);
     if (!rho.empty()) h = fnv1a(h, rho.data(), rho.size() * sizeof(double));
+    if (!muv.empty()) h = fnv1a(h, muv.data(), muv.size() * sizeof(double));
     if (h == 0) h = 1;
     const int64_t hs = hr_stride_for(m->N);
     uint64_t *Hr = static_cast<uint64_t *>(workspace);
@@ -325,6 +359,15 @@ ls_status ls_model_init(ls_model *m, void *workspace, size_t ws_bytes, void *str
                                             coef_offset_bytes(m->N, m->L));
     e = lsk::launch_coef_tables(m->L > 1 ? m->rho : nullptr, m->L, cs, coef, st);
     if (e != hipSuccess) return LS_ERR_DEVICE;
+    if (m->mu_vec) {
+        char *eb = static_cast<char *>(workspace) + emis_offset_bytes(m->N, m->L);
+        const size_t L = (size_t)m->L;
+        e = lsk::launch_emission_tables(
+            m->mu_vec, m->L, reinterpret_cast<double *>(eb),
+            reinterpret_cast<float *>(eb + 2 * L * sizeof(double)),
+            reinterpret_cast<double *>(eb + 2 * L * (sizeof(double) + sizeof(float))), st);
+        if (e != hipSuccess) return LS_ERR_DEVICE;
+    }
     m->hash = h;
     m->Hr = Hr;
     m->hr_stride = hs;
@@ -394,6 +437,7 @@ ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t 
     if (fwd->l == t) return T == 0 ? LS_OK : LS_ERR_ARG;
     Shape sh;
     if (!choose_shape(m->N, fwd->prec, &sh)) return LS_ERR_UNSUPPORTED;
+    if (m->mu_vec && fwd->prec == LS_FP32_F16STORE) return LS_ERR_UNSUPPORTED;
     SweepArgs a;
     std::memset(&a, 0, sizeof a);
     fill_scalars(a, m, fwd->prec, 0);
@@ -413,6 +457,7 @@ ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t 
     p.Hr = m->Hr;
     p.rho = m->L > 1 ? m->rho : reinterpret_cast<const double *>(m->Hr);  // only a discarded load when L == 1
     p.coef = coef_table(m, fwd->prec, 0);
+    emission_tables(m, fwd->prec, p);
     p.recipients = fwd->recipients;
     p.state = fwd->state;
     p.log_scale = fwd->log_scale;
@@ -449,6 +494,7 @@ ls_status ls_backward(ls_table *bck, const ls_model *m, int32_t t, const int32_t
     if (bck->l == t) return T == 0 ? LS_OK : LS_ERR_ARG;
     Shape sh;
     if (!choose_shape(m->N, bck->prec, &sh)) return LS_ERR_UNSUPPORTED;
+    if (m->mu_vec && bck->prec == LS_FP32_F16STORE) return LS_ERR_UNSUPPORTED;
     SweepArgs a;
     std::memset(&a, 0, sizeof a);
     fill_scalars(a, m, bck->prec, 1);
@@ -465,6 +511,7 @@ ls_status ls_backward(ls_table *bck, const ls_model *m, int32_t t, const int32_t
     p.Hr = m->Hr;
     p.rho = m->L > 1 ? m->rho : reinterpret_cast<const double *>(m->Hr);  // only a discarded load when L == 1
     p.coef = coef_table(m, bck->prec, 1);
+    emission_tables(m, bck->prec, p);
     p.recipients = bck->recipients;
     p.state = bck->state;
     p.log_scale = bck->log_scale;
@@ -545,6 +592,7 @@ ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R
     lsk::GradLayout lay;
     lsk::grad_workspace_bytes(m->N, m->L, R, (int)prec, &lay);
     char *ws = static_cast<char *>(workspace);
+    if (grad && m->mu_vec) return LS_ERR_UNSUPPORTED;  // the gradient takes a scalar mu
     hipStream_t st = as_stream(stream);
     const int32_t *rec = recipients;
     if (!rec) {

@@ -11,7 +11,8 @@ static hipError_t launch_every_one(const SweepPtrs &p, const SweepArgs &a, int n
     if (nwaves < 1 || nwaves > max_waves_for(NSLOT, PT::vgpr_per_slot)) return hipErrorInvalidValue;
     if (a.nblk < 1 || a.r0 < 0 || a.r0 + a.nblk > a.R) return hipErrorInvalidValue;
     hipLaunchKernelGGL((sweep_kernel<PT, NSLOT, 0, true>), dim3(a.nblk), dim3(64 * nwaves), 0, st,
-                       p.Hr, p.rho, p.coef, p.recipients, (typename PT::ST *)p.state,
+                       p.Hr, nullptr, nullptr, p.rho, p.coef, p.recipients,
+                       (typename PT::ST *)p.state,
                        p.log_scale, p.status, (typename PT::IO *)p.snap, a);
     return hipGetLastError();
 }

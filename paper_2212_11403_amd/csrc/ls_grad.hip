@@ -127,6 +127,8 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
                      double *lsc, bool every = false) -> hipError_t {
         SweepPtrs p;
         p.Hr = ga.Hr;
+        p.emis = nullptr;  // the gradient takes a scalar mu
+        p.lu_prefix = nullptr;
         p.rho = ga.rho;
         p.coef = prec == 0 ? nullptr : ga.coef_fwd32;
         p.recipients = ga.recipients;

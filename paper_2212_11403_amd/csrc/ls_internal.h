@@ -22,6 +22,9 @@ constexpr uint32_t kFlagBadRecipient = 2u;  // LS_FLAG_BAD_RECIPIENT
 // passed by value in this block.
 struct SweepPtrs {
     const uint64_t *Hr;         // [L][hr_stride] internal rows (see ls_model_init)
+    const void *emis;           // per-variant mu: [L][2] emission pairs in the sweep's
+                                // arithmetic type, else null (scalar mu)
+    const double *lu_prefix;    // per-variant mu, FP32 arithmetic: [L+1] log-unit prefix
     const double *rho;          // [L-1]
     const float *coef;          // [L][2] coefficient table of the precision and
                                 // direction (FP32 arithmetic), else null
@@ -180,6 +183,13 @@ hipError_t launch_coef_tables(const double *rho, int32_t L, const CoefScalars &c
 hipError_t launch_repack(const uint32_t *H, int64_t stride_words, int32_t N, int32_t L,
                          uint64_t *Hr, int64_t hr_stride, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
+// Emission tables of a per-variant mu (ls_misc.hip), after the coefficient
+// tables: [L][2] FP64 (match, mismatch) for the FP64 sweep, [L][2] FP32 pairs
+// divided by their larger member for sweeps in FP32 arithmetic, and the FP64
+// prefix sums [L+1] of the log of that divisor (entry l = sum over variants
+// below l).
+hipError_t launch_emission_tables(const double *mu_vec, int32_t L, double *em64, float *em32,
+                                  double *lu_prefix, hipStream_t st);
 // Recombination map (eq. rho) and its chain rule (ls_misc.hip)
 hipError_t launch_calc_rho(const double *cM, int32_t n, double s, double gamma, double *rho,
                            hipStream_t st);

@@ -394,6 +394,42 @@ hipError_t launch_symmetrise(const void *E, void *D, int32_t N, int32_t T, int i
 }
 
 // ---------------------------------------------------------------------------
+// Emission tables of a per-variant mu, from (1-H)(1-2mu)+mu (appendix A.3) in
+// FP64: the FP64 pair as is; the FP32 pair divided by its larger member and
+// rounded once, with the log of that divisor; then the prefix sums of those
+// logs in index order (one thread, so the sums are fixed).
+__global__ void __launch_bounds__(256)
+emission_tables_kernel(const double *__restrict__ mu_vec, int32_t L, double *__restrict__ em64,
+                       float *__restrict__ em32, double *__restrict__ lu_prefix) {
+    for (int l = threadIdx.x; l < L; l += 256) {
+        const double mu = mu_vec[l];
+        const double omu = (1.0 - 2.0 * mu) + mu;
+        em64[2 * l] = omu;
+        em64[2 * l + 1] = mu;
+        const double unit = omu >= mu ? omu : mu;
+        em32[2 * l] = (float)(omu / unit);
+        em32[2 * l + 1] = (float)(mu / unit);
+    }
+    if (threadIdx.x == 0) {
+        double acc = 0.0;
+        lu_prefix[0] = 0.0;
+        for (int l = 0; l < L; ++l) {
+            const double mu = mu_vec[l];
+            const double omu = (1.0 - 2.0 * mu) + mu;
+            acc += log(omu >= mu ? omu : mu);
+            lu_prefix[l + 1] = acc;
+        }
+    }
+}
+
+hipError_t launch_emission_tables(const double *mu_vec, int32_t L, double *em64, float *em32,
+                                  double *lu_prefix, hipStream_t st) {
+    hipLaunchKernelGGL(emission_tables_kernel, dim3(1), dim3(256), 0, st, mu_vec, L, em64, em32,
+                       lu_prefix);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Recombination map (eq. rho): rho_l = 1 - exp(-s m_l^gamma) with m_l =
 // cM_l / 100 the distance in Morgans (the argument is in centimorgans, as
 // the paper's CalcRho takes it), evaluated with expm1.

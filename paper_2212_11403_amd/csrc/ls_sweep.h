@@ -71,11 +71,16 @@ __device__ __forceinline__ SpecSlot special_slot(int q, int NF, int N, int g, bo
 // for the variants l0+1 .. t keep alpha at even offsets k = l - l0 (snap row
 // tgt_out[0] + k/2 - 1) and the c of every step (at snap + c_off, [k-1][R]);
 // the target list is not used.
-template <class PT, int NSLOT, int DIR, bool EVERY = false>
+// MUV: a mutation probability per variant; the emission pair of variant l is
+// read from `emis` ([L][2], in the arithmetic type) and, in FP32 arithmetic,
+// the logs of the divisors of the pairs emitted by this launch are added to
+// the log scale from the prefix table `lu_prefix` ([L+1]).
+template <class PT, int NSLOT, int DIR, bool EVERY = false, bool MUV = false>
 __global__ void __launch_bounds__(64 * max_waves_for(NSLOT, PT::vgpr_per_slot))
 __attribute__((amdgpu_waves_per_eu(
     sweep_waves_per_simd(sweep_budget_slots(NSLOT, PT::vgpr_per_slot, EVERY), PT::vgpr_per_slot))))
-sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
+sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__ emis,
+             const double *__restrict__ lu_prefix, const double *__restrict__ rho,
              const float *__restrict__ coef, const int32_t *__restrict__ recipients, typename PT::ST *__restrict__ state,
              double *__restrict__ log_scale, uint32_t *__restrict__ status,
              typename PT::IO *__restrict__ snap, const SweepArgs a) {
@@ -141,12 +146,27 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
     auto self_word = [&](int l) __attribute__((always_inline)) -> uint64_t {
         return Hr[(int64_t)l * a.hr_stride + self_off];
     };
-    // theta pair for a variant whose recipient word is `sw_bits`: value where
-    // the donor bit is 0, where it is 1
-    auto thetas = [&](uint64_t sw_bits, T &ta, T &tb) __attribute__((always_inline)) {
+    // emission pair (match, mismatch) of variant l with a per-variant mu;
+    // with a scalar mu the pair is (th_m, th_x) and (em, ex) is not used
+    auto emis_at = [&](int l, T &em, T &ex) __attribute__((always_inline)) {
+        if constexpr (MUV) {
+            em = emis[2 * l];
+            ex = emis[2 * l + 1];
+        } else {
+            em = ex = (T)0;
+        }
+    };
+    // theta pair for a variant whose recipient word is `sw_bits` (and whose
+    // emission pair is (em, ex)): value where the donor bit is 0, where it is 1
+    auto thetas = [&](uint64_t sw_bits, T em, T ex, T &ta, T &tb) __attribute__((always_inline)) {
         const bool rb = (sw_bits & self_bit) != 0;
-        ta = rb ? th_x : th_m;
-        tb = rb ? th_m : th_x;
+        if constexpr (MUV) {
+            ta = rb ? ex : em;
+            tb = rb ? em : ex;
+        } else {
+            ta = rb ? th_x : th_m;
+            tb = rb ? th_m : th_x;
+        }
     };
     // Lane partial sums of the column: even slots into acc0, odd into acc1,
     // starting from slots 0 and 1 (the entries are never -0, so this equals
@@ -162,10 +182,11 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
         return (s < NR) ? row[reg_base + s] : row[spec_off[s - NR]];
     };
     // v <- theta^l (.) (c v + b); returns this lane's partial sum
-    auto step = [&](int l, uint64_t sw_bits, T c, T b_s) __attribute__((always_inline)) -> T {
+    auto step = [&](int l, uint64_t sw_bits, T em, T ex, T c, T b_s)
+                    __attribute__((always_inline)) -> T {
         const uint64_t *row = Hr + (int64_t)l * a.hr_stride;
         T ta, tb;
-        thetas(sw_bits, ta, tb);
+        thetas(sw_bits, em, ex, ta, tb);
         const T b = in_vgpr(b_s);
         T acc0, acc1 = (T)0;
 #pragma unroll
@@ -190,8 +211,9 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
     // v <- theta^l (.) v; returns this lane's partial sum
     auto emit = [&](int l) __attribute__((always_inline)) -> T {
         const uint64_t *row = Hr + (int64_t)l * a.hr_stride;
-        T ta, tb;
-        thetas(row[self_off], ta, tb);
+        T em, ex, ta, tb;
+        emis_at(l, em, ex);
+        thetas(row[self_off], em, ex, ta, tb);
         T acc0, acc1 = (T)0;
 #pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
@@ -369,17 +391,19 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
             const rsrc_t rs_c =
                 make_rsrc(snap + a.c_off, (uint32_t)((a.t - a.l0) * a.R * (int)sizeof(IO)));
             const int c_voff = threadIdx.x == 0 ? r * (int)sizeof(IO) : 0x7ffffff0;
-            T A_nx, B_nx;
+            T A_nx, B_nx, em_nx, ex_nx;
             coefs_at(l <= lmax ? l : lmax, A_nx, B_nx);
+            emis_at(l <= lmax ? l : lmax, em_nx, ex_nx);
             uint64_t w_nx = self_word(l <= lmax ? l : lmax);
             T c_nx = coef_c(A_nx, S);
             for (; l <= a.t; ++l) {
-                const T c = c_nx, B = B_nx;
+                const T c = c_nx, B = B_nx, em = em_nx, ex = ex_nx;
                 const uint64_t wb = w_nx;
                 const int ln = l < lmax ? l + 1 : lmax;
                 coefs_at(ln, A_nx, B_nx);
+                emis_at(ln, em_nx, ex_nx);
                 w_nx = self_word(ln);
-                T part = step(l, wb, c, B);
+                T part = step(l, wb, em, ex, c, B);
                 buf_store((IO)c, rs_c, c_voff, (l - a.l0 - 1) * a.R * (int)sizeof(IO));
                 S = block_sum<MAXW>(part, red, parity, wave, nwaves);
                 c_nx = coef_c(A_nx, S);
@@ -410,17 +434,19 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
             }
         } else for (;;) {
             const int lend = kt < a.nt ? a.tgt_l[kt] : a.t;
-            T A_nx, B_nx;
+            T A_nx, B_nx, em_nx, ex_nx;
             coefs_at(l <= lmax ? l : lmax, A_nx, B_nx);
+            emis_at(l <= lmax ? l : lmax, em_nx, ex_nx);
             uint64_t w_nx = self_word(l <= lmax ? l : lmax);
             T c_nx = coef_c(A_nx, S);
             for (; l <= lend; ++l) {
-                const T c = c_nx, b = B_nx;
+                const T c = c_nx, b = B_nx, em = em_nx, ex = ex_nx;
                 const uint64_t wb = w_nx;
                 const int ln = l < lmax ? l + 1 : lmax;
                 coefs_at(ln, A_nx, B_nx);
+                emis_at(ln, em_nx, ex_nx);
                 w_nx = self_word(ln);
-                T part = step(l, wb, c, b);
+                T part = step(l, wb, em, ex, c, b);
                 S = block_sum<MAXW>(part, red, parity, wave, nwaves);
                 // the next variant's c (its A was read at the top), next to
                 // the log-scale update so that the two chains overlap
@@ -443,19 +469,21 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
                 const int lend = kt < a.nt ? a.tgt_l[kt] : a.t;
                 // the coefficients and the recipient's own word are read one
                 // variant ahead
-                T A_nx, B_nx;
+                T A_nx, B_nx, em_nx, ex_nx;
                 coefs_at(l, A_nx, B_nx);
+                emis_at(l, em_nx, ex_nx);
                 uint64_t w_nx = self_word(l);
                 for (; l > lend; --l) {
-                    const T A = A_nx, B = B_nx;
+                    const T A = A_nx, B = B_nx, em = em_nx, ex = ex_nx;
                     const uint64_t wb = w_nx;
                     const int ln = l > 0 ? l - 1 : 0;
                     coefs_at(ln, A_nx, B_nx);
+                    emis_at(ln, em_nx, ex_nx);
                     w_nx = self_word(ln);
                     const T c = coef_c(A, S);
                     const T b = B;
                     account(S);
-                    part = step(l, wb, c, b);
+                    part = step(l, wb, em, ex, c, b);
                     S = block_sum<MAXW>(part, red, parity, wave, nwaves);
                 }
                 // l == lend: a target or the stopping variant; keep beta^l
@@ -476,8 +504,19 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
     store_state();
     // ---- epilogue: log scale and status ------------------------------------
     if (threadIdx.x == 0) {
-        const double ls = base + (log(prod) + (double)expo * 0.69314718055994530942) +
-                          (double)nlog * a.log_off;
+        double ls = base + (log(prod) + (double)expo * 0.69314718055994530942) +
+                    (double)nlog * a.log_off;
+        if constexpr (MUV && sizeof(T) == 4) {
+            // logs of the divisors of the emission pairs applied here: the
+            // forward applies variants first .. t, the backward lstart .. t+1
+            if constexpr (DIR == 0) {
+                const int first = a.l0 < 0 ? 0 : a.l0 + 1;
+                if (a.t >= first) ls += lu_prefix[a.t + 1] - lu_prefix[first];
+            } else {
+                const int lstart = a.l0 < 0 ? a.L - 1 : a.l0;
+                if (a.t < lstart) ls += lu_prefix[lstart + 1] - lu_prefix[a.t + 1];
+            }
+        }
         log_scale[r] = ls;
         if (!isfinite(ls)) status[r] |= kFlagNonfinite;
     }

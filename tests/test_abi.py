@@ -47,7 +47,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_struct_layouts_match_header():
     from paper_2212_11403_amd._lib import LsModel, LsTable
-    assert ctypes.sizeof(LsModel) == 72
+    assert ctypes.sizeof(LsModel) == 80
     assert ctypes.sizeof(LsTable) == 56
 
 
@@ -58,9 +58,12 @@ def test_host_only_calls(lib):
     assert lib.ls_model_workspace_bytes(1, 10) == 0
     # internal rows: two copies of floor(N/64) words plus the partial word,
     # padded to 64 B, the whole rounded up to 256 B; then four tables of L
-    # FP32 coefficient pairs
-    assert lib.ls_model_workspace_bytes(200, 10) == 768 + 4 * 10 * 2 * 4
-    assert lib.ls_model_workspace_bytes(10000, 3) == 7680 + 4 * 3 * 2 * 4
+    # FP32 coefficient pairs; then the emission tables of a per-variant mu
+    # (L FP64 pairs, L FP32 pairs, L + 1 FP64 prefix sums)
+    def emis(L):
+        return L * 16 + L * 8 + (L + 1) * 8
+    assert lib.ls_model_workspace_bytes(200, 10) == 768 + 4 * 10 * 2 * 4 + emis(10)
+    assert lib.ls_model_workspace_bytes(10000, 3) == 7680 + 4 * 3 * 2 * 4 + emis(3)
 
 
 def test_validation_errors_before_any_device_work(lib):
