@@ -50,6 +50,8 @@ def bind(path: str):
     lib.lso_pass_v.restype = ctypes.c_int
     lib.lso_gradient.argtypes = [P, i64, i32, i32, P, f64, P, i32, P, P, P, P, i32]
     lib.lso_gradient.restype = ctypes.c_int
+    lib.lso_gradient_v.argtypes = [P, i64, i32, i32, P, P, P, i32, P, P, P, P, P, i32]
+    lib.lso_gradient_v.restype = ctypes.c_int
     lib.lso_symmetrise.argtypes = [P, i32, P]
     lib.lso_symmetrise.restype = None
     lib.lso_calc_rho.argtypes = [P, i32, f64, f64, P]
@@ -123,7 +125,9 @@ def run_gradient(H, N, L, rho, mu, recipients, nthreads=None, lib=None):
     """Per-recipient log-likelihood and its gradient w.r.t. rho (L-1) and mu.
 
     Returns dict(loglik [R], grad_rho [R][L-1], grad_mu [R], status [R]).
-    Holds an L x N FP64 forward table per thread.
+    With a per-variant ``mu`` (L values) also grad_mu_l [R][L], the
+    derivative w.r.t. each mu^l (grad_mu is their sum). Holds an L x N FP64
+    forward table per thread.
     """
     lib = lib or _load()
     H = np.ascontiguousarray(H, dtype=np.uint32)
@@ -134,6 +138,17 @@ def run_gradient(H, N, L, rho, mu, recipients, nthreads=None, lib=None):
     gm = np.empty(R)
     ll = np.empty(R)
     st = np.zeros(R, dtype=np.int32)
+    if np.ndim(mu) == 1:
+        muv = np.ascontiguousarray(mu, dtype=np.float64)
+        if muv.size != L:
+            raise ValueError("a per-variant mu needs L values")
+        gml = np.zeros((R, L))
+        rc = lib.lso_gradient_v(_ptr(H), H.shape[1], N, L, _ptr(rho), _ptr(muv), _ptr(rec), R,
+                                _ptr(g) if L > 1 else None, _ptr(gml), _ptr(gm), _ptr(ll),
+                                _ptr(st), nthreads or default_threads())
+        if rc != 0:
+            raise ValueError("oracle rejected its arguments")
+        return dict(loglik=ll, grad_rho=g, grad_mu=gm, grad_mu_l=gml, status=st)
     rc = lib.lso_gradient(_ptr(H), H.shape[1], N, L, _ptr(rho), float(mu), _ptr(rec), R,
                           _ptr(g) if L > 1 else None, _ptr(gm), _ptr(ll), _ptr(st),
                           nthreads or default_threads())

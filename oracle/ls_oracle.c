@@ -244,10 +244,12 @@ static int recipient_pass(const lso_model *m, int i, const lso_out *o, double *b
     return status;
 }
 
-/* Gradient of log P(h_i | h_-i) w.r.t. rho[0..L-2] and mu. Stores the full
- * forward table (L x N) for this recipient. Returns the status bits. */
+/* Gradient of log P(h_i | h_-i) w.r.t. rho[0..L-2] and mu; with grad_mu_l
+ * (may be NULL) also the derivative w.r.t. each mu^l, l = 0..L-1 (their sum
+ * is *grad_mu). Stores the full forward table (L x N) for this recipient.
+ * Returns the status bits. */
 static int recipient_gradient(const lso_model *m, int i, double *grad_rho, double *grad_mu,
-                              double *loglik)
+                              double *grad_mu_l, double *loglik)
 {
     const int N = m->N, L = m->L;
     int status = 0;
@@ -274,12 +276,17 @@ static int recipient_gradient(const lso_model *m, int i, double *grad_rho, doubl
     for (int l = L - 1; l >= 0; --l) {
         /* mu term at l from p^l */
         posterior(m, i, alpha + (int64_t)l * N, beta, p);
+        double gl = 0.0;
         for (int j = 0; j < N; ++j) {
             if (j == i)
                 continue;
             int Hm = allele(m, l, j) ^ allele(m, l, i);
-            gmu += Hm ? p[j] / mu_at(m, l) : -p[j] / (1.0 - mu_at(m, l));
+            double t = Hm ? p[j] / mu_at(m, l) : -p[j] / (1.0 - mu_at(m, l));
+            gmu += t;
+            gl += t;
         }
+        if (grad_mu_l)
+            grad_mu_l[l] = gl;
         if (l == 0)
             break;
         /* rho_{l-1} term uses alpha^{l-1}, theta^l, beta^l */
@@ -322,6 +329,7 @@ typedef struct {
     /* gradient */
     double *grad_rho_rows; /* [R][L-1] */
     double *grad_mu;       /* [R] */
+    double *grad_mu_rows;  /* [R][L] per-variant mu terms, or NULL */
 } lso_job;
 
 static void *pass_worker(void *arg)
@@ -394,7 +402,8 @@ static void *grad_worker(void *arg)
     for (int r = jb->tid; r < jb->R; r += jb->nth) {
         double gm = 0, ll = 0;
         int st = recipient_gradient(m, jb->recips[r], jb->grad_rho_rows + (int64_t)r * (m->L - 1),
-                                    &gm, &ll);
+                                    &gm, jb->grad_mu_rows ? jb->grad_mu_rows + (int64_t)r * m->L : NULL,
+                                    &ll);
         jb->grad_mu[r] = gm;
         if (jb->llf)
             jb->llf[r] = ll;
@@ -518,6 +527,34 @@ int lso_gradient(const uint32_t *H, int64_t stride, int32_t N, int32_t L, const 
     proto.R = R;
     proto.grad_rho_rows = grad_rho_rows;
     proto.grad_mu = grad_mu;
+    proto.llf = loglik;
+    proto.status = status;
+    return run_jobs(&proto, nthreads, grad_worker);
+}
+
+/* As lso_gradient with a per-variant mutation probability mu_vec[0..L-1];
+ * grad_mu_rows [R][L] receives d log P / d mu^l per recipient and grad_mu [R]
+ * their sum over l. */
+int lso_gradient_v(const uint32_t *H, int64_t stride, int32_t N, int32_t L, const double *rho,
+                   const double *mu_vec, const int32_t *recips, int32_t R, double *grad_rho_rows,
+                   double *grad_mu_rows, double *grad_mu, double *loglik, int32_t *status,
+                   int32_t nthreads)
+{
+    lso_model m = {H, stride, N, L, rho, 0.0, mu_vec};
+    if (!mu_vec || check_model(&m) || R < 0 ||
+        (R > 0 && (!recips || !grad_mu || !grad_mu_rows || !loglik)) || (L > 1 && !grad_rho_rows))
+        return 1;
+    for (int r = 0; r < R; ++r)
+        if (recips[r] < 0 || recips[r] >= N)
+            return 1;
+    lso_job proto;
+    memset(&proto, 0, sizeof proto);
+    proto.m = &m;
+    proto.recips = recips;
+    proto.R = R;
+    proto.grad_rho_rows = grad_rho_rows;
+    proto.grad_mu = grad_mu;
+    proto.grad_mu_rows = grad_mu_rows;
     proto.llf = loglik;
     proto.status = status;
     return run_jobs(&proto, nthreads, grad_worker);

@@ -90,6 +90,45 @@ def test_oracle_per_variant_mu_matches_enumeration(L, N, seed, mnum, rnum):
         np.testing.assert_allclose(res["P"][:, i, :], post, rtol=1e-12, atol=1e-15)
 
 
+@pytest.mark.parametrize("L,N,seed,mnum,rnum", [
+    (5, 4, 6, [1, 3, 2, 8, 1], [3, 17, 1, 29]),
+    (6, 3, 7, [4, 1, 1, 16, 2, 5], [5, 0, 31, 12, 32]),
+    (4, 5, 8, [2, 20, 1, 5], [7, 2, 11]),
+])
+def test_oracle_per_variant_mu_gradient_matches_enumeration(L, N, seed, mnum, rnum):
+    """d log P / d rho_l and d log P / d mu^l for every variant, by exact
+    differentiation of the enumerated likelihood."""
+    h01 = _rand_h(L, N, seed)
+    rho = [Fraction(k, 32) for k in rnum]
+    mu = [Fraction(k, 32) for k in mnum]
+    g = oracle.run_gradient(pack_haplotypes(h01), N, L, np.array([float(r) for r in rho]),
+                            np.array([float(m) for m in mu]), np.arange(N, dtype=np.int32))
+    for i in range(N):
+        ex = enumerate_exact(h01.tolist(), rho, mu, i)
+        logP = np.log(float(ex["P"]))
+        assert abs(g["loglik"][i] - logP) <= 1e-13 * abs(logP) + 1e-14
+        dr = np.array([float(x) for x in ex["dlogP_drho"]])
+        np.testing.assert_allclose(g["grad_rho"][i], dr, rtol=1e-10, atol=1e-12)
+        dm = np.array([float(x) for x in ex["dlogP_dmu_l"]])
+        np.testing.assert_allclose(g["grad_mu_l"][i], dm, rtol=1e-10, atol=1e-10)
+        assert abs(g["grad_mu"][i] - dm.sum()) <= 1e-10 * np.abs(dm).sum() + 1e-10
+
+
+def test_oracle_constant_mu_vector_gradient_equals_scalar():
+    """A constant vector gives the scalar model's gradient bit for bit (the
+    terms are added in the same order), and the per-variant terms add up to
+    it."""
+    L, N = 30, 8
+    h01 = _rand_h(L, N, 14)
+    rho = rho_from_spacings(np.random.default_rng(14).exponential(0.05, L - 1))
+    rec = np.arange(N, dtype=np.int32)
+    a = oracle.run_gradient(pack_haplotypes(h01), N, L, rho, 0.02, rec)
+    b = oracle.run_gradient(pack_haplotypes(h01), N, L, rho, np.full(L, 0.02), rec)
+    for k in ("loglik", "grad_rho", "grad_mu"):
+        assert np.array_equal(a[k], b[k]), k
+    np.testing.assert_allclose(b["grad_mu_l"].sum(axis=1), b["grad_mu"], rtol=1e-12)
+
+
 def test_oracle_constant_mu_vector_equals_scalar():
     L, N = 40, 9
     h01 = _rand_h(L, N, 12)
