@@ -98,10 +98,11 @@ typedef struct {
     /* optional, set by the caller before ls_model_init: */
     const double *mu_vec; /* device, [L] mutation probability per variant (the
                              paper's vector mu, section 3.4), each in [0, 1],
-                             or NULL: mu at every variant. Used by decoding and
-                             the log-likelihood in LS_FP64 and LS_FP32; the
-                             FP16-stored tables and the gradient return
-                             LS_ERR_UNSUPPORTED for such a model. */
+                             or NULL: mu at every variant. Used by decoding,
+                             the log-likelihood and its gradient (then one
+                             d/d mu^l per variant) in LS_FP64 and LS_FP32;
+                             FP16-stored tables return LS_ERR_UNSUPPORTED
+                             for such a model. */
 } ls_model;
 
 /* Device bytes of the workspace ls_model_init lays the internal haplotype
@@ -203,9 +204,11 @@ ls_status ls_distance_symmetrise(const void *E, void *D, int32_t N, int32_t T,
 /* Log-likelihood of each recipient, log P(h_i | h_-i) = log F^{L-1}, their
  * sum (the product-of-approximate-conditionals log-likelihood over all
  * recipients, section 1) and, if grad_rho / grad_mu are not NULL, the
- * gradient of that sum with respect to rho[0..L-2] and mu.
+ * gradient of that sum with respect to rho[0..L-2] and mu (with a
+ * per-variant mu_vec: with respect to each mu^l).
  * recipients: device, [R] (NULL = all N haplotypes in order, R must be N).
- * loglik: device [R] double (may be NULL); pac, grad_mu: device [1] double;
+ * loglik: device [R] double (may be NULL); pac: device [1] double;
+ * grad_mu: device double, [1] for a scalar mu, [L] with mu_vec;
  * grad_rho: device [L-1] double. The sum over recipients is taken in a fixed
  * order, so results do not depend on scheduling. The gradient is the exact
  * score (not a finite difference), computed with forward checkpoints every
@@ -218,7 +221,8 @@ ls_status ls_distance_symmetrise(const void *E, void *D, int32_t N, int32_t T,
  * 256-byte aligned; owned by the caller, contents undefined after the call.
  * About e R N (1.5 sqrt(L) + 3) + 8 R L bytes (e = 4 for FP32, 8 for FP64):
  * checkpoints, the kept half of one segment's forward vectors, the
- * per-variant rho terms of every recipient.
+ * per-variant rho terms of every recipient (and with mu_vec 8 R L more
+ * for the per-variant mu terms).
  * Errors: LS_ERR_ARG, LS_ERR_WORKSPACE (missing, too small or misaligned),
  * LS_ERR_UNSUPPORTED, LS_ERR_DEVICE. */
 ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R,

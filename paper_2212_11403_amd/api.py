@@ -228,8 +228,8 @@ def rho_map_grad(cM, s: float, gamma: float, grad_rho, stream=None) -> torch.Ten
 
 def loglik_grad(model: Model, recipients=None, prec="fp32", grad: bool = True, stream=None):
     """Per-recipient log-likelihood, their sum (PAC) and optionally the
-    gradient of the sum w.r.t. rho (L-1) and mu. Returns a dict of device
-    tensors."""
+    gradient of the sum w.r.t. rho (L-1) and mu (1 value, or L with a
+    per-variant mu). Returns a dict of device tensors."""
     lib = _lib.load()
     pc = prec_code(prec)
     dev = model.device
@@ -241,7 +241,8 @@ def loglik_grad(model: Model, recipients=None, prec="fp32", grad: bool = True, s
     ll = torch.empty(R, dtype=torch.float64, device=dev)
     pac = torch.empty(1, dtype=torch.float64, device=dev)
     g_rho = torch.empty(max(model.L - 1, 1), dtype=torch.float64, device=dev) if grad else None
-    g_mu = torch.empty(1, dtype=torch.float64, device=dev) if grad else None
+    n_mu = 1 if model.mu_vec is None else model.L
+    g_mu = torch.empty(n_mu, dtype=torch.float64, device=dev) if grad else None
     nbytes = lib.ls_loglik_grad_workspace_bytes(ctypes.byref(model.c), R, pc)
     ws = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
     check(lib.ls_loglik_grad(ctypes.byref(model.c), _p(rec), R, pc, _p(ll), _p(pac), _p(g_rho),

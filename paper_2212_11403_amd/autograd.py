@@ -22,13 +22,15 @@ from . import api
 class PACLoglik(torch.autograd.Function):
     """PACLoglik.apply(rho, mu, H, N, prec="fp32", recipients=None) -> scalar.
 
-    rho: float64 device tensor [L-1]; mu: float64 0-d tensor; H: packed
-    haplotypes (device int32 [L][stride] or numpy uint32).
+    rho: float64 device tensor [L-1]; mu: float64 0-d tensor, or [L] (one
+    per variant); H: packed haplotypes (device int32 [L][stride] or numpy
+    uint32).
     """
 
     @staticmethod
     def forward(ctx, rho, mu, H, N, prec="fp32", recipients=None):
-        model = api.Model(H, int(N), rho.detach().to(torch.float64), float(mu))
+        mu_arg = float(mu) if mu.dim() == 0 else mu.detach().to(torch.float64)
+        model = api.Model(H, int(N), rho.detach().to(torch.float64), mu_arg)
         out = api.loglik_grad(model, recipients, prec, grad=False)
         ctx.model = model
         ctx.prec = prec

@@ -571,7 +571,7 @@ ls_status ls_rho_map_grad(const double *cM, int32_t n, double s, double gamma,
 
 size_t ls_loglik_grad_workspace_bytes(const ls_model *m, int32_t R, ls_precision prec) {
     if (check_model(m) != LS_OK || R < 1 || !valid_prec(prec)) return 0;
-    return lsk::grad_workspace_bytes(m->N, m->L, R, (int)prec, nullptr);
+    return lsk::grad_workspace_bytes(m->N, m->L, R, (int)prec, m->mu_vec != nullptr, nullptr);
 }
 
 ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R,
@@ -584,15 +584,15 @@ ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R
     if (!recipients && R != m->N) return LS_ERR_ARG;
     const bool grad = grad_rho || grad_mu;
     if (grad && (!grad_mu || (m->L > 1 && !grad_rho))) return LS_ERR_ARG;
-    const size_t need = lsk::grad_workspace_bytes(m->N, m->L, R, (int)prec, nullptr);
+    const bool muv = m->mu_vec != nullptr;
+    const size_t need = lsk::grad_workspace_bytes(m->N, m->L, R, (int)prec, muv, nullptr);
     if (!workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
         return LS_ERR_WORKSPACE;
     Shape sh;
     if (!choose_shape(m->N, prec, &sh, grad)) return LS_ERR_UNSUPPORTED;
     lsk::GradLayout lay;
-    lsk::grad_workspace_bytes(m->N, m->L, R, (int)prec, &lay);
+    lsk::grad_workspace_bytes(m->N, m->L, R, (int)prec, muv, &lay);
     char *ws = static_cast<char *>(workspace);
-    if (grad && m->mu_vec) return LS_ERR_UNSUPPORTED;  // the gradient takes a scalar mu
     hipStream_t st = as_stream(stream);
     const int32_t *rec = recipients;
     if (!rec) {
@@ -628,6 +628,15 @@ ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R
     ga.seg = lay.seg;
     ga.nseg = lay.nseg;
     ga.mu = m->mu;
+    {
+        SweepPtrs ep;
+        emission_tables(m, prec, ep);
+        ga.emis = ep.emis;
+        ga.lu_prefix = ep.lu_prefix;
+        SweepPtrs e64;
+        emission_tables(m, LS_FP64, e64);
+        ga.em64 = static_cast<const double *>(e64.emis);
+    }
     ga.chunk = sweep_chunk();
     if (!choose_shape(m->N, prec, &ga.fwd_shape)) return LS_ERR_UNSUPPORTED;
     ga.ws = ws;

@@ -13,7 +13,8 @@ namespace lsk {
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-size_t grad_workspace_bytes(int32_t N, int32_t L, int32_t R, int prec, GradLayout *lay) {
+size_t grad_workspace_bytes(int32_t N, int32_t L, int32_t R, int prec, bool muv,
+                            GradLayout *lay) {
     GradLayout g;
     const size_t es = prec == 0 ? 8 : (prec == 1 ? 4 : 2);
     const size_t gs = prec == 0 ? 8 : 4;  // checkpoint / segment element
@@ -39,6 +40,8 @@ size_t grad_workspace_bytes(int32_t N, int32_t L, int32_t R, int prec, GradLayou
     off = align256(off + sizeof(double) * (size_t)(L > 1 ? L - 1 : 1) * R);
     g.off_gmu = off;
     off = align256(off + sizeof(double) * (size_t)R);
+    g.off_gmul = off;
+    if (muv) off = align256(off + sizeof(double) * (size_t)L * R);
     g.off_lsc = off;
     off = align256(off + sizeof(double) * (size_t)R);
     g.off_ybuf = off;
@@ -122,13 +125,14 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
     char *ws = ga.ws;
     const int64_t RN = (int64_t)ga.R * ga.N;
     const size_t es = prec == 0 ? 8 : 4;
-    const Emissions em = sweep_emissions(ga.mu, prec != 0);
+    Emissions em = sweep_emissions(ga.mu, prec != 0);
+    if (ga.emis) em.log_unit = 0.0;  // per variant, from the prefix table
     auto sweep = [&](int dir, int l0, int t, const int32_t *tl, int nt, void *state, void *snap,
                      double *lsc, bool every = false) -> hipError_t {
         SweepPtrs p;
         p.Hr = ga.Hr;
-        p.emis = nullptr;  // the gradient takes a scalar mu
-        p.lu_prefix = nullptr;
+        p.emis = ga.emis;
+        p.lu_prefix = ga.lu_prefix;
         p.rho = ga.rho;
         p.coef = prec == 0 ? nullptr : ga.coef_fwd32;
         p.recipients = ga.recipients;
@@ -232,8 +236,12 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
                            grad_rho);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(sum_rows_kernel, dim3(1), dim3(64), 0, st,
-                       reinterpret_cast<const double *>(ws + Ly.off_gmu), ga.R, 1, grad_mu);
+    if (ga.emis)
+        hipLaunchKernelGGL(sum_rows_kernel, dim3(ga.L), dim3(64), 0, st,
+                           reinterpret_cast<const double *>(ws + Ly.off_gmul), ga.R, ga.L, grad_mu);
+    else
+        hipLaunchKernelGGL(sum_rows_kernel, dim3(1), dim3(64), 0, st,
+                           reinterpret_cast<const double *>(ws + Ly.off_gmu), ga.R, 1, grad_mu);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return launch_loglik_sum(ll, ga.R, loglik, pac, st);
 }

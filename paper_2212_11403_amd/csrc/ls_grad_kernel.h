@@ -24,6 +24,10 @@ namespace lsk {
 //   M_l = sum_{j mismatching at l} alpha^l_j beta^l_j / sum_j alpha^l_j beta^l_j
 //   d log P / d mu += M_l / mu - (1 - M_l) / (1 - mu).
 // Per-variant rho terms go to grow[l][r]; the mu term accumulates in gmu[r].
+// MUV (a mutation probability per variant): theta^l is the pair of variant
+// l from `emis` (the sweep's table), and d log P / d mu^l = M_l / mu^l -
+// (1 - M_l) / (1 - mu^l), with the FP64 pair from `em64`, goes to
+// gmul[l][r].
 //
 // The recompute keeps alpha only at even offsets from s0 (offset 0 is the
 // checkpoint) and the c of every forward step. The pass therefore walks the
@@ -54,14 +58,16 @@ __host__ __device__ constexpr int grad_kernel_waves(int nslot, int vgpr_per_slot
                                                                 : 4);
 }
 
-template <class PT, int NSLOT, bool NARROW>
+template <class PT, int NSLOT, bool NARROW, bool MUV = false>
 __global__ void __launch_bounds__(64 * grad_kernel_waves(NSLOT, PT::vgpr_per_slot, NARROW))
 grad_seg_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
                 const float *__restrict__ coef, const float *__restrict__ coefb,
                 const int32_t *__restrict__ recipients,
                 const typename PT::T *__restrict__ alpha0, const typename PT::T *__restrict__ aseg,
                 const typename PT::T *__restrict__ cval, typename PT::T *__restrict__ ybuf,
-                double *__restrict__ grow, double *__restrict__ gmu, const GradSegArgs a) {
+                double *__restrict__ grow, double *__restrict__ gmu,
+                const typename PT::T *__restrict__ emis, const double *__restrict__ em64,
+                double *__restrict__ gmul, const GradSegArgs a) {
 #pragma clang fp contract(off)
     using T = typename PT::T;
     constexpr int K = special_slots(NSLOT);
@@ -134,7 +140,15 @@ grad_seg_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
         const uint64_t *row = Hr + (int64_t)ll * a.hr_stride;
         const bool rb = (row[self_off] & self_bit) != 0;
         const uint64_t flip = rb ? ~0ull : 0ull;
-        const T ta = rb ? th_x : th_m, tb = rb ? th_m : th_x;
+        T ta, tb;
+        if constexpr (MUV) {
+            const T em = emis[2 * ll], ex = emis[2 * ll + 1];
+            ta = rb ? ex : em;
+            tb = rb ? em : ex;
+        } else {
+            ta = rb ? th_x : th_m;
+            tb = rb ? th_m : th_x;
+        }
         T d = 0, sa = 0, mn = 0, sy = 0;
 #pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
@@ -169,9 +183,14 @@ grad_seg_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
         if constexpr (sizeof(T) == 4) bf = coef[2 * ll + 1];
         else bf = rho[ll - 1] * a.bmul;
     };
-    auto mu_term = [&](double Mn, double Z) __attribute__((always_inline)) {
+    auto mu_term = [&](int ll, double Mn, double Z) __attribute__((always_inline)) {
         const double M = Mn / Z;
-        gm += M * a.inv_mu - (1.0 - M) * a.inv_omu;
+        if constexpr (MUV) {
+            if (lane == 0)
+                gmul[(int64_t)ll * a.R + r] = M / em64[2 * ll + 1] - (1.0 - M) / em64[2 * ll];
+        } else {
+            gm += M * a.inv_mu - (1.0 - M) * a.inv_omu;
+        }
     };
     // variant ll after the first of the pass: the rho term and the mu term.
     // beta^ll = c y^{ll+1} + b with c = (1 - rho_ll)(N-1) / Sy and b = rho_ll;
@@ -202,7 +221,7 @@ grad_seg_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
             const double d = (double)q[0], Sa = (double)q[1];
             const double pss = pi * Sa * (double)Sy;
             if (lane == 0) grow[(int64_t)ll * a.R + r] = (pss - d) / ((1.0 - rr) * d + rr * pss);
-            mu_term((double)q[2], (double)c * d + (double)b * Sa);
+            mu_term(ll, (double)q[2], (double)c * d + (double)b * Sa);
         }
         Sy = q[3];
     };
@@ -213,7 +232,7 @@ grad_seg_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
         T q[4];
         step(derive, ll, (T)0, (T)1, src, cf, bf, q);
         block_sum4<MAXW>(q, red, parity, wave);
-        if (wave == 0) mu_term((double)q[2], (double)q[1]);
+        if (wave == 0) mu_term(ll, (double)q[2], (double)q[1]);
         Sy = q[3];
     };
 
@@ -316,9 +335,16 @@ hipError_t launch_grad_seg(const GradArgs &ga, const GradSegArgs &sa, int nwaves
     double *gmu = reinterpret_cast<double *>(ws + L.off_gmu);
     const float *coef = sizeof(T) == 4 ? ga.coef_fwd32 : nullptr;
     const float *coefb = sizeof(T) == 4 ? ga.coef_bwd32 : nullptr;
-    hipLaunchKernelGGL((grad_seg_kernel<PT, NSLOT, NARROW>), dim3(ga.R), dim3(64 * nwaves), 0, st,
-                       ga.Hr, ga.rho, coef, coefb, ga.recipients, alpha0, aseg, cval, ybuf, grow,
-                       gmu, sa);
+    if (ga.emis)
+        hipLaunchKernelGGL((grad_seg_kernel<PT, NSLOT, NARROW, true>), dim3(ga.R),
+                           dim3(64 * nwaves), 0, st, ga.Hr, ga.rho, coef, coefb, ga.recipients,
+                           alpha0, aseg, cval, ybuf, grow, gmu,
+                           reinterpret_cast<const T *>(ga.emis), ga.em64,
+                           reinterpret_cast<double *>(ws + L.off_gmul), sa);
+    else
+        hipLaunchKernelGGL((grad_seg_kernel<PT, NSLOT, NARROW>), dim3(ga.R), dim3(64 * nwaves), 0,
+                           st, ga.Hr, ga.rho, coef, coefb, ga.recipients, alpha0, aseg, cval, ybuf,
+                           grow, gmu, nullptr, nullptr, nullptr, sa);
     return hipGetLastError();
 }
 

@@ -218,13 +218,15 @@ struct GradLayout {
     size_t off_cval;    // [seg][R] c of the forward step at each offset 1, 2, ..
     size_t off_grow;    // double [L-1][R] per-recipient d log P / d rho
     size_t off_gmu;     // double [R]
+    size_t off_gmul;    // double [L][R] per-recipient d log P / d mu^l (vector mu)
     size_t off_lsc;     // double [R] scratch log scale of the recompute sweeps
     size_t off_ybuf;    // [R][N] backward vector handed between segments
     size_t total;
     int32_t seg, nseg;
 };
 // Fills *lay (if not null) and returns the workspace size.
-size_t grad_workspace_bytes(int32_t N, int32_t L, int32_t R, int prec, GradLayout *lay);
+size_t grad_workspace_bytes(int32_t N, int32_t L, int32_t R, int prec, bool muv,
+                            GradLayout *lay);
 
 struct GradArgs {
     const uint64_t *Hr;
@@ -238,6 +240,11 @@ struct GradArgs {
     int32_t chunk;      // variants per launch of the checkpointing forward sweep
     Shape fwd_shape;    // its shape: the one a plain forward sweep of N uses
     double mu;
+    // per-variant mu (else all null): the emission pairs in the arithmetic
+    // type, the FP64 pairs (1-mu^l, mu^l) and, for FP32, the log-unit prefix
+    const void *emis;
+    const double *em64;
+    const double *lu_prefix;
     char *ws;
     GradLayout lay;
 };

@@ -11,7 +11,7 @@ import oracle
 from lsinputs import pack_haplotypes, rho_from_spacings
 
 from _gpu import (F32_LOGLIK_RTOL, F32_POST_ATOL, F64_ATOL_LOG, F64_ATOL_PROB, F64_RTOL,
-                  need_gpu, rel_close)
+                  forced_shape, need_gpu, rel_close)
 
 pytestmark = pytest.mark.gpu
 
@@ -161,7 +161,7 @@ def test_vector_mu_unsupported_and_invalid(ls):
         ls.decode(m, [3], "f16", want=("P",))
     assert e.value.code == 4  # LS_ERR_UNSUPPORTED
     with pytest.raises(ls.LsError) as e:
-        ls.loglik_grad(m, prec="fp32", grad=True)
+        ls.loglik_grad(m, prec="f16", grad=False)
     assert e.value.code == 4
     with pytest.raises(ValueError):
         ls.Model(H, N, rho, mu[:-1])
@@ -180,3 +180,89 @@ def test_vector_mu_unsupported_and_invalid(ls):
     with pytest.raises(ls.LsError) as e:
         ls.forward(t, m2, 5)
     assert e.value.code == 3  # LS_ERR_STATE
+
+
+# ---------------------------------------------------------------------------
+# gradient with respect to each mu^l (and rho) with a per-variant mu
+
+def _grad_case(N, L, seed):
+    """As _case, with mu^l > 0 everywhere (d/d mu^l has a 1/mu^l term)."""
+    H, rho, mu = _case(N, L, seed)
+    mu[mu == 0.0] = 1e-3
+    return H, rho, mu
+
+
+def _check_grad(ls, H, N, L, rho, mu, rec, prec):
+    ref = oracle.run_gradient(H, N, L, rho, mu, rec)
+    out = ls.loglik_grad(ls.Model(H, N, rho, mu), rec, prec, grad=True)
+    ll = ref["loglik"].sum()
+    tol_ll = 1e-12 if prec == "fp64" else F32_LOGLIK_RTOL
+    assert abs(float(out["pac"].item()) - ll) <= tol_ll * abs(ll)
+    if L > 1:
+        g = out["grad_rho"].cpu().numpy()
+        scale = max(np.abs(ref["grad_rho"]).sum(axis=0).max(), 1.0)
+        assert np.abs(g - ref["grad_rho"].sum(axis=0)).max() <= (1e-10 if prec == "fp64" else 1e-6) * scale
+    # d/d mu^l sums one term M/mu - (1-M)/(1-mu) per recipient; its rounding
+    # scales with the two parts, M/mu + (1-M)/(1-mu), before they cancel
+    # (M, the mismatch share of the posterior, recovered from the term)
+    gml = ref["grad_mu_l"]
+    M = (gml + 1.0 / (1.0 - mu)) / (1.0 / mu + 1.0 / (1.0 - mu))
+    parts = (M / mu + (1.0 - M) / (1.0 - mu)).sum(axis=0)
+    got = out["grad_mu"].cpu().numpy()
+    assert got.shape == (L,)
+    err = np.abs(got - gml.sum(axis=0)) / parts
+    print(f"{prec} N={N} L={L}: max error of d/d mu^l relative to its parts {err.max():.2e}")
+    # observed: up to 2e-14 (FP64) and 3e-7 (FP32)
+    assert err.max() <= (1e-12 if prec == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("N,L", [(2, 50), (40, 300), (130, 200), (40, 1), (40, 2), (40, 7),
+                                 (40, 10)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_vector_mu_gradient_vs_oracle(ls, N, L, prec):
+    """All recipients; L = 1, 2, 7 and 10 give one-variant and two-variant
+    segments and segments that end at the last variant."""
+    H, rho, mu = _grad_case(N, L, seed=3 * N + L)
+    _check_grad(ls, H, N, L, rho, mu, np.arange(N, dtype=np.int32), prec)
+
+
+@pytest.mark.parametrize("prec,N,ns,nw", [("fp32", 10000, 16, 13), ("fp64", 4000, 8, 13)])
+def test_vector_mu_gradient_wide_groups(ls, prec, N, ns, nw):
+    L = 61
+    H, rho, mu = _grad_case(N, L, seed=N + 1)
+    rec = np.array([0, 63, N // 2, N - 1], np.int32)
+    with forced_shape(ns, nw):
+        _check_grad(ls, H, N, L, rho, mu, rec, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_vector_mu_gradient_constant_vector(ls, prec):
+    """A constant vector: the rho gradient equals the scalar model's bit for
+    bit, the per-variant mu terms add up to the scalar d/d mu, and log P is
+    the same with and without the gradient."""
+    N, L = 200, 400
+    H, rho, _ = _grad_case(N, L, seed=17)
+    ms = ls.Model(H, N, rho, 0.004)
+    mv = ls.Model(H, N, rho, np.full(L, 0.004))
+    a = ls.loglik_grad(ms, None, prec, grad=True)
+    b = ls.loglik_grad(mv, None, prec, grad=True)
+    c = ls.loglik_grad(mv, None, prec, grad=False)
+    assert np.array_equal(a["grad_rho"].cpu().numpy(), b["grad_rho"].cpu().numpy())
+    assert np.array_equal(b["loglik"].cpu().numpy(), c["loglik"].cpu().numpy())
+    gs, gv = float(a["grad_mu"].item()), float(b["grad_mu"].sum().item())
+    assert abs(gs - gv) <= 1e-12 * float(b["grad_mu"].abs().sum().item())
+    x, y = float(a["pac"].item()), float(b["pac"].item())
+    assert abs(x - y) <= (0 if prec == "fp64" else 1e-12) * abs(x)
+
+
+def test_vector_mu_autograd(ls):
+    import torch
+    N, L = 60, 80
+    H, rho, mu = _grad_case(N, L, seed=5)
+    r = torch.tensor(rho, dtype=torch.float64, device="cuda", requires_grad=True)
+    m = torch.tensor(mu, dtype=torch.float64, device="cuda", requires_grad=True)
+    pac = ls.PACLoglik.apply(r, m, H, N, "fp64")
+    pac.backward()
+    ref = oracle.run_gradient(H, N, L, rho, mu, np.arange(N, dtype=np.int32))
+    rel_close(m.grad.cpu().numpy(), ref["grad_mu_l"].sum(axis=0), 1e-9, 1e-9)
+    rel_close(r.grad.cpu().numpy(), ref["grad_rho"].sum(axis=0), 1e-9, 1e-9)
