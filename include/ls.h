@@ -51,7 +51,7 @@ typedef enum {
     LS_ERR_STATE = 3,       /* table at the wrong variant or direction, or
                                built with another model (hash mismatch) */
     LS_ERR_UNSUPPORTED = 4, /* N too large for this precision on one GPU, or a
-                               per-variant mu where it is not supported */
+                               feature this precision does not offer */
     LS_ERR_DEVICE = 5,      /* the HIP runtime reported an error */
     LS_ERR_WORKSPACE = 6,   /* workspace missing or too small */
     LS_WARN_NONFINITE = 16  /* returned by ls_status_check only */
@@ -100,9 +100,8 @@ typedef struct {
                              paper's vector mu, section 3.4), each in [0, 1],
                              or NULL: mu at every variant. Used by decoding,
                              the log-likelihood and its gradient (then one
-                             d/d mu^l per variant) in LS_FP64 and LS_FP32;
-                             FP16-stored tables return LS_ERR_UNSUPPORTED
-                             for such a model. */
+                             d/d mu^l per variant) in every precision that
+                             offers them. */
 } ls_model;
 
 /* Device bytes of the workspace ls_model_init lays the internal haplotype

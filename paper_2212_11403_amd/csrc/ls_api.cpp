@@ -437,7 +437,6 @@ ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t 
     if (fwd->l == t) return T == 0 ? LS_OK : LS_ERR_ARG;
     Shape sh;
     if (!choose_shape(m->N, fwd->prec, &sh)) return LS_ERR_UNSUPPORTED;
-    if (m->mu_vec && fwd->prec == LS_FP32_F16STORE) return LS_ERR_UNSUPPORTED;
     SweepArgs a;
     std::memset(&a, 0, sizeof a);
     fill_scalars(a, m, fwd->prec, 0);
@@ -494,7 +493,6 @@ ls_status ls_backward(ls_table *bck, const ls_model *m, int32_t t, const int32_t
     if (bck->l == t) return T == 0 ? LS_OK : LS_ERR_ARG;
     Shape sh;
     if (!choose_shape(m->N, bck->prec, &sh)) return LS_ERR_UNSUPPORTED;
-    if (m->mu_vec && bck->prec == LS_FP32_F16STORE) return LS_ERR_UNSUPPORTED;
     SweepArgs a;
     std::memset(&a, 0, sizeof a);
     fill_scalars(a, m, bck->prec, 1);
