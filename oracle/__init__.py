@@ -52,6 +52,11 @@ def bind(path: str):
     lib.lso_gradient.restype = ctypes.c_int
     lib.lso_gradient_v.argtypes = [P, i64, i32, i32, P, P, P, i32, P, P, P, P, P, i32]
     lib.lso_gradient_v.restype = ctypes.c_int
+    lib.lso_pass_x.argtypes = [P, i64, i32, i32, P, f64, P, P, P, i32, P, i32,
+                               P, P, P, P, P, P, P, P, P, i32]
+    lib.lso_pass_x.restype = ctypes.c_int
+    lib.lso_gradient_x.argtypes = [P, i64, i32, i32, P, f64, P, P, P, i32, P, P, P, P, P, i32]
+    lib.lso_gradient_x.restype = ctypes.c_int
     lib.lso_symmetrise.argtypes = [P, i32, P]
     lib.lso_symmetrise.restype = None
     lib.lso_calc_rho.argtypes = [P, i32, f64, f64, P]
@@ -78,9 +83,21 @@ def default_threads() -> int:
     return max(1, min(n, int(os.environ.get("LSO_THREADS", n))))
 
 
-def run_pass(H, N, L, rho, mu, recipients, targets=(), want=("P", "E"), nthreads=None, lib=None):
+def _prior_arg(prior, N):
+    """The prior copying matrix Pi as an N x N array with Pi[j, i] the prior
+    probability that recipient i copies donor j (column i belongs to
+    recipient i), laid out for the library (row i of the buffer = column i)."""
+    Pi = np.asarray(prior, dtype=np.float64)
+    if Pi.shape != (N, N):
+        raise ValueError("the prior matrix must be N x N")
+    return np.ascontiguousarray(Pi.T)
+
+
+def run_pass(H, N, L, rho, mu, recipients, targets=(), want=("P", "E"), nthreads=None, lib=None,
+             prior=None):
     """Forward/backward pass for each recipient. ``mu`` is a scalar or a
-    per-variant array of L values.
+    per-variant array of L values; ``prior`` the N x N prior copying matrix
+    Pi (Pi[j, i]: recipient i copies donor j), or None for the uniform prior.
 
     Returns a dict with ``llf``/``llb`` (forward and backward log-likelihood,
     shape [R]) and, for each name in ``want`` among A (alpha), B (beta), P
@@ -102,7 +119,20 @@ def run_pass(H, N, L, rho, mu, recipients, targets=(), want=("P", "E"), nthreads
     out["llf"] = np.empty(R)
     out["llb"] = np.empty(R)
     out["status"] = np.zeros(R, dtype=np.int32)
-    if np.ndim(mu) == 1:
+    if prior is not None:
+        Pt = _prior_arg(prior, N)
+        muv = None
+        if np.ndim(mu) == 1:
+            muv = np.ascontiguousarray(mu, dtype=np.float64)
+            if muv.size != L:
+                raise ValueError("a per-variant mu needs L values")
+        rc = lib.lso_pass_x(_ptr(H), H.shape[1], N, L, _ptr(rho),
+                            0.0 if muv is not None else float(mu), _ptr(muv), _ptr(Pt),
+                            _ptr(rec), R, _ptr(tg), T, _ptr(out["A"]), _ptr(out["B"]),
+                            _ptr(out["P"]), _ptr(out["E"]), _ptr(out["logF"]), _ptr(out["logG"]),
+                            _ptr(out["llf"]), _ptr(out["llb"]), _ptr(out["status"]),
+                            nthreads or default_threads())
+    elif np.ndim(mu) == 1:
         muv = np.ascontiguousarray(mu, dtype=np.float64)
         if muv.size != L:
             raise ValueError("a per-variant mu needs L values")
@@ -121,13 +151,13 @@ def run_pass(H, N, L, rho, mu, recipients, targets=(), want=("P", "E"), nthreads
     return {k: v for k, v in out.items() if v is not None}
 
 
-def run_gradient(H, N, L, rho, mu, recipients, nthreads=None, lib=None):
+def run_gradient(H, N, L, rho, mu, recipients, nthreads=None, lib=None, prior=None):
     """Per-recipient log-likelihood and its gradient w.r.t. rho (L-1) and mu.
 
     Returns dict(loglik [R], grad_rho [R][L-1], grad_mu [R], status [R]).
     With a per-variant ``mu`` (L values) also grad_mu_l [R][L], the
-    derivative w.r.t. each mu^l (grad_mu is their sum). Holds an L x N FP64
-    forward table per thread.
+    derivative w.r.t. each mu^l (grad_mu is their sum). ``prior`` as in
+    run_pass. Holds an L x N FP64 forward table per thread.
     """
     lib = lib or _load()
     H = np.ascontiguousarray(H, dtype=np.uint32)
@@ -138,6 +168,24 @@ def run_gradient(H, N, L, rho, mu, recipients, nthreads=None, lib=None):
     gm = np.empty(R)
     ll = np.empty(R)
     st = np.zeros(R, dtype=np.int32)
+    if prior is not None:
+        Pt = _prior_arg(prior, N)
+        muv, gml = None, None
+        if np.ndim(mu) == 1:
+            muv = np.ascontiguousarray(mu, dtype=np.float64)
+            if muv.size != L:
+                raise ValueError("a per-variant mu needs L values")
+            gml = np.zeros((R, L))
+        rc = lib.lso_gradient_x(_ptr(H), H.shape[1], N, L, _ptr(rho),
+                                0.0 if muv is not None else float(mu), _ptr(muv), _ptr(Pt),
+                                _ptr(rec), R, _ptr(g) if L > 1 else None, _ptr(gml), _ptr(gm),
+                                _ptr(ll), _ptr(st), nthreads or default_threads())
+        if rc != 0:
+            raise ValueError("oracle rejected its arguments")
+        out = dict(loglik=ll, grad_rho=g, grad_mu=gm, status=st)
+        if gml is not None:
+            out["grad_mu_l"] = gml
+        return out
     if np.ndim(mu) == 1:
         muv = np.ascontiguousarray(mu, dtype=np.float64)
         if muv.size != L:

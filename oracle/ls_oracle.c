@@ -14,7 +14,10 @@
  * Definitions used (paper section 2.1 and 2.2, appendix A):
  *   emission  theta^l_j = (1 - H)(1 - 2 mu) + mu, H = 1{h_j^l != h_i^l}
  *             (eq. emission, in the form of appendix A.3)
- *   prior     pi_j = 1/(N-1) for j != i, pi_i = 0 (uniform copying prior)
+ *   prior     pi_j = Pi_ji, column i of the prior copying matrix Pi (section
+ *             2.1; left stochastic, Pi_ii = 0), or by default the uniform
+ *             prior pi_j = 1/(N-1) for j != i, pi_i = 0. The transition is
+ *             T_jk = rho pi_k + (1-rho) 1{j=k} (eq. transition)
  *   forward   alpha^0 = theta^0 pi                                (eq. fwd0)
  *             alpha^l = theta^l ((1-rho_{l-1}) alpha^{l-1}/sum(alpha^{l-1})
  *                                 + rho_{l-1} pi)                 (eq. fwd1)
@@ -57,6 +60,8 @@ typedef struct {
     const double *rho; /* [L-1] */
     double mu;
     const double *mu_vec; /* [L] per-variant mu^l, or NULL: mu at every variant */
+    const double *Pi;     /* [N][N], Pi[i*N + j] = Pi_ji (column i: the prior of
+                             recipient i), or NULL: the uniform prior */
 } lso_model;
 
 /* allele of haplotype j at variant l: bit (j mod 32) of word floor(j/32) */
@@ -79,9 +84,12 @@ static double theta(const lso_model *m, int l, int j, int i)
     return (double)(1 - Hm) * (1.0 - 2.0 * mu) + mu;
 }
 
+/* Pi_ji; the diagonal is 0 by convention (self copying is excluded) */
 static double prior(const lso_model *m, int j, int i)
 {
-    return j == i ? 0.0 : 1.0 / (double)(m->N - 1);
+    if (j == i)
+        return 0.0;
+    return m->Pi ? m->Pi[(int64_t)i * m->N + j] : 1.0 / (double)(m->N - 1);
 }
 
 static double sum_vec(const double *v, int n)
@@ -474,6 +482,19 @@ int lso_pass_v(const uint32_t *H, int64_t stride, int32_t N, int32_t L, const do
                       nthreads);
 }
 
+/* The general pass: a scalar mu or mu_vec (if not NULL), and the prior
+ * matrix Pi (NULL: uniform). */
+int lso_pass_x(const uint32_t *H, int64_t stride, int32_t N, int32_t L, const double *rho,
+               double mu, const double *mu_vec, const double *Pi, const int32_t *recips,
+               int32_t R, const int32_t *targets, int32_t T, double *A, double *B, double *P,
+               double *E, double *logF, double *logG, double *llf, double *llb, int32_t *status,
+               int32_t nthreads)
+{
+    lso_model m = {H, stride, N, L, rho, mu, mu_vec, Pi};
+    return pass_model(&m, recips, R, targets, T, A, B, P, E, logF, logG, llf, llb, status,
+                      nthreads);
+}
+
 static int pass_model(const lso_model *mp, const int32_t *recips, int32_t R,
                       const int32_t *targets, int32_t T, double *A, double *B, double *P,
                       double *E, double *logF, double *logG, double *llf, double *llb,
@@ -555,6 +576,34 @@ int lso_gradient_v(const uint32_t *H, int64_t stride, int32_t N, int32_t L, cons
     proto.grad_rho_rows = grad_rho_rows;
     proto.grad_mu = grad_mu;
     proto.grad_mu_rows = grad_mu_rows;
+    proto.llf = loglik;
+    proto.status = status;
+    return run_jobs(&proto, nthreads, grad_worker);
+}
+
+/* The general gradient: a scalar mu or mu_vec (if not NULL; then
+ * grad_mu_rows [R][L] is required), and the prior matrix Pi (NULL:
+ * uniform). */
+int lso_gradient_x(const uint32_t *H, int64_t stride, int32_t N, int32_t L, const double *rho,
+                   double mu, const double *mu_vec, const double *Pi, const int32_t *recips,
+                   int32_t R, double *grad_rho_rows, double *grad_mu_rows, double *grad_mu,
+                   double *loglik, int32_t *status, int32_t nthreads)
+{
+    lso_model m = {H, stride, N, L, rho, mu, mu_vec, Pi};
+    if (check_model(&m) || R < 0 || (R > 0 && (!recips || !grad_mu || !loglik)) ||
+        (L > 1 && !grad_rho_rows) || (mu_vec && R > 0 && !grad_mu_rows))
+        return 1;
+    for (int r = 0; r < R; ++r)
+        if (recips[r] < 0 || recips[r] >= N)
+            return 1;
+    lso_job proto;
+    memset(&proto, 0, sizeof proto);
+    proto.m = &m;
+    proto.recips = recips;
+    proto.R = R;
+    proto.grad_rho_rows = grad_rho_rows;
+    proto.grad_mu = grad_mu;
+    proto.grad_mu_rows = mu_vec ? grad_mu_rows : NULL;
     proto.llf = loglik;
     proto.status = status;
     return run_jobs(&proto, nthreads, grad_worker);

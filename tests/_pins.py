@@ -27,26 +27,29 @@ def _theta_exact(h, l, j, i, mu):
     return mu if h[l][j] != h[l][i] else 1 - mu
 
 
-def enumerate_exact(h, rho, mu, i):
+def enumerate_exact(h, rho, mu, i, prior=None):
     """Exact P(h_i | h_-i), posterior marginals p[l][j] and the derivatives
     d log P / d rho_l (length L-1) and d log P / d mu, by summing over all
     (N-1)^L copying paths. ``h`` is an L x N nested list of 0/1; ``rho`` a list
     of L-1 Fractions; ``mu`` a Fraction, or a list of L Fractions (one per
     variant), in which case ``dlogP_dmu_l`` holds the derivative with respect
-    to each."""
+    to each. ``prior``: an N x N nested list of Fractions, prior[j][i] the
+    prior probability that recipient i copies donor j (its diagonal is not
+    used), or None for the uniform prior."""
     L, N = len(h), len(h[0])
     mus = list(mu) if isinstance(mu, (list, tuple)) else [mu] * L
     donors = [j for j in range(N) if j != i]
-    pi = Fraction(1, N - 1)
+    pi_of = [Fraction(1, N - 1) if prior is None else prior[j][i] for j in range(N)]
     P = Fraction(0)
     marg = [[Fraction(0)] * N for _ in range(L)]
     dP_drho = [Fraction(0)] * (L - 1)
     dP_dmu = [Fraction(0)] * L
     for path in itertools.product(donors, repeat=L):
         em = [_theta_exact(h, l, path[l], i, mus[l]) for l in range(L)]
-        tr = [rho[l] * pi + (1 - rho[l]) * (1 if path[l] == path[l + 1] else 0)
+        tr = [rho[l] * pi_of[path[l + 1]] + (1 - rho[l]) * (1 if path[l] == path[l + 1] else 0)
               for l in range(L - 1)]
-        prob = pi
+        start = pi_of[path[0]]
+        prob = start
         for e in em:
             prob *= e
         for t in tr:
@@ -54,10 +57,10 @@ def enumerate_exact(h, rho, mu, i):
         P += prob
         for l in range(L):
             marg[l][path[l]] += prob
-        # d prob / d rho_l: replace T_l by its derivative pi - 1{j=k}
+        # d prob / d rho_l: replace T_l by its derivative pi_k - 1{j=k}
         for l in range(L - 1):
-            d = pi - (1 if path[l] == path[l + 1] else 0)
-            rest = pi
+            d = pi_of[path[l + 1]] - (1 if path[l] == path[l + 1] else 0)
+            rest = start
             for e in em:
                 rest *= e
             for m, t in enumerate(tr):
@@ -67,7 +70,7 @@ def enumerate_exact(h, rho, mu, i):
         # d prob / d mu: product rule over the emissions, d theta/d mu = +-1
         for l in range(L):
             d = 1 if h[l][path[l]] != h[l][i] else -1
-            rest = pi
+            rest = start
             for m, e in enumerate(em):
                 if m != l:
                     rest *= e

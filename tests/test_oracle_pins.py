@@ -397,3 +397,96 @@ def test_packing_round_trip_and_bit_order():
 def test_targets_are_evenly_spaced():
     t = evenly_spaced_targets(2000, 10)
     assert list(t) == [100, 300, 500, 700, 900, 1100, 1300, 1500, 1700, 1900]
+
+
+# ---------------------------------------------------------------------------
+# non-uniform prior copying matrix Pi (section 2.1; column i belongs to
+# recipient i, Pi_ii = 0, columns sum to 1)
+
+def _rand_prior(N, seed):
+    """Rational left stochastic N x N matrix with a zero diagonal."""
+    W = np.random.default_rng(seed).integers(1, 10, size=(N, N))
+    Pi = [[Fraction(0)] * N for _ in range(N)]
+    for i in range(N):
+        tot = sum(int(W[j, i]) for j in range(N) if j != i)
+        for j in range(N):
+            if j != i:
+                Pi[j][i] = Fraction(int(W[j, i]), tot)
+    return Pi
+
+
+@pytest.mark.parametrize("L,N,seed,mnum,rnum", [
+    (5, 4, 21, 4, [3, 17, 1, 29]),
+    (4, 5, 22, [2, 9, 1, 5], [7, 2, 11]),
+    (6, 3, 23, 6, [5, 0, 31, 12, 32]),
+])
+def test_oracle_prior_matrix_matches_enumeration(L, N, seed, mnum, rnum):
+    """Posteriors, both log-likelihoods and the gradient (rho, and mu as a
+    scalar or per variant) under a random prior matrix, by enumeration."""
+    h01 = _rand_h(L, N, seed)
+    Pi = _rand_prior(N, seed)
+    Pf = np.array([[float(x) for x in row] for row in Pi])
+    rho = [Fraction(k, 32) for k in rnum]
+    mu = [Fraction(k, 32) for k in mnum] if isinstance(mnum, list) else Fraction(mnum, 32)
+    mu_arg = np.array([float(m) for m in mu]) if isinstance(mu, list) else float(mu)
+    rf = np.array([float(r) for r in rho])
+    H = pack_haplotypes(h01)
+    rec = np.arange(N, dtype=np.int32)
+    res = oracle.run_pass(H, N, L, rf, mu_arg, rec, np.arange(L, dtype=np.int32), want=("P",),
+                          prior=Pf)
+    g = oracle.run_gradient(H, N, L, rf, mu_arg, rec, prior=Pf)
+    for i in range(N):
+        ex = enumerate_exact(h01.tolist(), rho, mu, i, prior=Pi)
+        logP = np.log(float(ex["P"]))
+        for v in (res["llf"][i], res["llb"][i], g["loglik"][i]):
+            assert abs(v - logP) <= 1e-13 * abs(logP) + 1e-14
+        post = np.array([[float(x) for x in row] for row in ex["post"]])
+        np.testing.assert_allclose(res["P"][:, i, :], post, rtol=1e-12, atol=1e-15)
+        dr = np.array([float(x) for x in ex["dlogP_drho"]])
+        np.testing.assert_allclose(g["grad_rho"][i], dr, rtol=1e-10, atol=1e-12)
+        assert abs(g["grad_mu"][i] - float(ex["dlogP_dmu"])) <= 1e-10 * abs(float(ex["dlogP_dmu"])) + 1e-10
+        if isinstance(mu, list):
+            dm = np.array([float(x) for x in ex["dlogP_dmu_l"]])
+            np.testing.assert_allclose(g["grad_mu_l"][i], dm, rtol=1e-10, atol=1e-10)
+
+
+def test_oracle_uniform_prior_matrix_equals_default():
+    L, N = 30, 9
+    h01 = _rand_h(L, N, 31)
+    rho = rho_from_spacings(np.random.default_rng(31).exponential(0.05, L - 1))
+    Pf = np.full((N, N), 1.0 / (N - 1))
+    np.fill_diagonal(Pf, 0.0)
+    H, rec, tg = pack_haplotypes(h01), np.arange(N, dtype=np.int32), np.array([2, 17], np.int32)
+    a = oracle.run_pass(H, N, L, rho, 0.02, rec, tg, want=("P", "B", "logF", "logG"))
+    b = oracle.run_pass(H, N, L, rho, 0.02, rec, tg, want=("P", "B", "logF", "logG"), prior=Pf)
+    for k in ("P", "B", "logF", "logG", "llf", "llb"):
+        assert np.array_equal(a[k], b[k]), k
+    ga = oracle.run_gradient(H, N, L, rho, 0.02, rec)
+    gb = oracle.run_gradient(H, N, L, rho, 0.02, rec, prior=Pf)
+    for k in ("loglik", "grad_rho", "grad_mu"):
+        assert np.array_equal(ga[k], gb[k]), k
+
+
+def test_oracle_prior_matrix_full_recombination_closed_form():
+    """With rho = 1 between every pair of variants the copied donor is
+    redrawn from the prior at each variant, independently: p^l_j =
+    Pi_ji theta^l_j / sum_k Pi_ki theta^l_k and P = prod_l sum_k Pi_ki
+    theta^l_k."""
+    L, N, mu = 12, 40, 0.07
+    rng = np.random.default_rng(41)
+    h01 = (rng.random((L, N)) < 0.4).astype(np.uint8)
+    W = rng.random((N, N)) ** 3
+    np.fill_diagonal(W, 0.0)
+    Pf = W / W.sum(axis=0, keepdims=True)
+    rec = np.array([0, 5, 39], np.int32)
+    res = oracle.run_pass(pack_haplotypes(h01), N, L, np.ones(L - 1), mu, rec,
+                          np.arange(L, dtype=np.int32), want=("P",), prior=Pf)
+    for r, i in enumerate(rec):
+        ll = 0.0
+        for l in range(L):
+            th = np.where(h01[l] == h01[l, i], 1.0 - mu, mu)
+            w = Pf[:, i] * th
+            np.testing.assert_allclose(res["P"][l, r], w / w.sum(), rtol=1e-12, atol=1e-300)
+            ll += np.log(w.sum())
+        assert abs(res["llf"][r] - ll) <= 1e-12 * abs(ll)
+        assert abs(res["llb"][r] - ll) <= 1e-12 * abs(ll)
