@@ -27,8 +27,8 @@ MUTANTS = {
     "forward_rho_index": ("double r = m->rho[l - 1];\n    for (int j = 0; j < m->N; ++j) {\n        if (j == i) {\n            next[j] = 0.0;",
                           "double r = m->rho[l > 1 ? l - 2 : 0];\n    for (int j = 0; j < m->N; ++j) {\n        if (j == i) {\n            next[j] = 0.0;"),
     "emission_swapped": ("(double)(1 - Hm) * (1.0 - 2.0 * mu) + mu", "(double)(Hm) * (1.0 - 2.0 * mu) + mu"),
-    "prior_keeps_self": ("return j == i ? 0.0 : 1.0 / (double)(m->N - 1);",
-                         "return 1.0 / (double)(m->N - 1);"),
+    "prior_keeps_self": ("    if (j == i)\n        return 0.0;\n    return m->Pi",
+                         "    return m->Pi"),
     "backward_theta_index": ("cur[j] = (1.0 - r) * next[j] * theta(m, l + 1, j, i) / g + r;",
                              "cur[j] = (1.0 - r) * next[j] * theta(m, l, j, i) / g + r;"),
     "backward_rho_index": ("double r = m->rho[l];", "double r = m->rho[l + 1 < m->L - 1 ? l + 1 : l];"),
