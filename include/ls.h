@@ -90,7 +90,7 @@ typedef struct {
     const double *rho;    /* device, [L-1], each in [0, 1]; may be NULL if L == 1 */
     double mu;            /* in [0, 1] */
     /* set by ls_model_init */
-    uint64_t hash;        /* hash of (N, L, rho, mu, mu_vec); tables remember it */
+    uint64_t hash;        /* hash of (N, L, rho, mu, mu_vec, prior); tables remember it */
     const uint64_t *Hr;   /* device: internal row layout in the workspace */
     int64_t hr_stride;    /* 64-bit words per internal row */
     int32_t nf;           /* number of full 64-haplotype words: floor(N/64) */
@@ -102,12 +102,25 @@ typedef struct {
                              the log-likelihood and its gradient (then one
                              d/d mu^l per variant) in every precision that
                              offers them. */
+    const double *prior;  /* device, [N][N] prior copying matrix Pi (section
+                             2.1), row i = column i of Pi: prior[i*N + j] =
+                             Pi_ji, the prior probability that recipient i
+                             copies donor j; every entry in [0, 1], each row
+                             summing to 1 without its diagonal (which is not
+                             used: self copying is excluded), else
+                             ls_model_init returns LS_ERR_ARG. NULL: the
+                             uniform prior 1/(N-1). Used by decoding and the
+                             log-likelihood in LS_FP64 and LS_FP32 with a
+                             scalar mu; other uses return
+                             LS_ERR_UNSUPPORTED. The caller keeps it alive
+                             and unchanged while the model is in use. */
 } ls_model;
 
 /* Device bytes of the workspace ls_model_init lays the internal haplotype
  * rows (about 2 N L / 8 bytes), the per-variant FP32 transition
- * coefficients of the sweeps (32 L bytes) and the per-variant emission
- * tables for a vector mu (32 L + 8 bytes) into. */
+ * coefficients of the sweeps (32 L bytes), the per-variant emission
+ * tables for a vector mu (32 L + 8 bytes) and the checks of a prior matrix
+ * (16 N bytes) into. */
 size_t ls_model_workspace_bytes(int32_t N, int32_t L);
 
 /* Validates the inputs, computes the hash and builds the internal rows in

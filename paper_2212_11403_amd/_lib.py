@@ -48,6 +48,7 @@ class LsModel(ctypes.Structure):
         ("nf", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
         ("mu_vec", ctypes.c_void_p),
+        ("prior", ctypes.c_void_p),
     ]
 
 

@@ -58,9 +58,12 @@ class Model:
     H: L x stride packed haplotypes (numpy uint32 or a device tensor).
     rho: L-1 recombination probabilities; mu: mutation probability, a scalar
     or one value per variant (L values; section 3.4 allows either).
+    prior: optional N x N prior copying matrix Pi (section 2.1), Pi[j, i] the
+    prior probability that recipient i copies donor j (columns sum to 1, the
+    diagonal is not used); None for the uniform prior.
     """
 
-    def __init__(self, H, N: int, rho, mu, device="cuda", stream=None):
+    def __init__(self, H, N: int, rho, mu, device="cuda", stream=None, prior=None):
         lib = _lib.load()
         dev = torch.device(device)
         if isinstance(H, np.ndarray):
@@ -91,6 +94,15 @@ class Model:
                 raise ValueError("a per-variant mu must have L entries")
             self.c.mu = 0.0
             self.c.mu_vec = self.mu_vec.data_ptr()
+        self.prior = None
+        if prior is not None:
+            Pi = prior.to(torch.float64) if torch.is_tensor(prior) else \
+                torch.as_tensor(np.asarray(prior, dtype=np.float64))
+            if tuple(Pi.shape) != (int(N), int(N)):
+                raise ValueError("the prior matrix must be N x N")
+            # row i of the library's buffer is column i of Pi
+            self.prior = Pi.to(dev).t().contiguous()
+            self.c.prior = self.prior.data_ptr()
         nbytes = lib.ls_model_workspace_bytes(int(N), L)
         if nbytes == 0:
             raise ValueError("invalid N or L")

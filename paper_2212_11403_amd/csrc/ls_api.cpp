@@ -47,6 +47,13 @@ size_t emis_offset_bytes(int32_t N, int32_t L) {
     return coef_offset_bytes(N, L) + (size_t)lsk::kCoefTables * 2 * (size_t)L * sizeof(float);
 }
 
+// Byte offset of the [N][2] checks of a prior matrix, after the emission
+// tables.
+size_t prior_stats_offset_bytes(int32_t N, int32_t L) {
+    return emis_offset_bytes(N, L) + (size_t)L * (2 * sizeof(double) + 2 * sizeof(float)) +
+           (size_t)(L + 1) * sizeof(double);
+}
+
 uint64_t fnv1a(uint64_t h, const void *data, size_t n) {
     const unsigned char *p = static_cast<const unsigned char *>(data);
     for (size_t i = 0; i < n; ++i) {
@@ -87,9 +94,10 @@ std::vector<int> menu(int prec, bool grad = false) {
 
 // Does (nslot, nwaves) place every donor word of N haplotypes? Regular
 // slots must all hold full words and all words must be placed.
-bool shape_fits(int32_t N, int prec, int nslot, int nwaves) {
+bool shape_fits(int32_t N, int prec, int nslot, int nwaves, bool prior = false) {
     if (!in_menu(prec, nslot)) return false;
-    if (nwaves < 1 || nwaves > lsk::max_waves_for(nslot, vgpr_per_slot(prec))) return false;
+    const int vps = lsk::sweep_slot_vgprs(vgpr_per_slot(prec), prior);
+    if (nwaves < 1 || nwaves > lsk::max_waves_for(nslot, vps)) return false;
     const int NW = (N + 63) / 64, NF = N / 64;
     const int K = lsk::special_slots(nslot);
     return (int64_t)nwaves * (nslot - K) <= NF && (int64_t)nwaves * nslot >= NW;
@@ -119,10 +127,10 @@ double shape_cost(int32_t N, int prec, int ns, int nw, int wps = 0) {
 // order. The gradient first looks among the groups its prefetching adjoint
 // kernel runs (grad_max_waves), costed with that kernel's occupancy; only
 // when none of them places N does it take the sweep's wider groups.
-bool choose_shape(int32_t N, int prec, Shape *out, bool grad = false) {
+bool choose_shape(int32_t N, int prec, Shape *out, bool grad = false, bool prior = false) {
     if (const char *env = std::getenv("LS_FORCE_SHAPE")) {
         int ns = 0, nw = 0;
-        if (std::sscanf(env, "%d,%d", &ns, &nw) == 2 && shape_fits(N, prec, ns, nw)) {
+        if (std::sscanf(env, "%d,%d", &ns, &nw) == 2 && shape_fits(N, prec, ns, nw, prior)) {
             *out = Shape{ns, nw};
             return true;
         }
@@ -130,10 +138,13 @@ bool choose_shape(int32_t N, int prec, Shape *out, bool grad = false) {
     const int vps = vgpr_per_slot(prec);
     for (int pass = grad ? 0 : 1; pass < 2; ++pass) {
         auto ok = [&](int ns, int nw) {
-            return shape_fits(N, prec, ns, nw) && (pass == 1 || nw <= lsk::grad_max_waves(ns, vps));
+            return shape_fits(N, prec, ns, nw, prior) &&
+                   (pass == 1 || nw <= lsk::grad_max_waves(ns, vps));
         };
         auto cost = [&](int ns, int nw) {
-            return shape_cost(N, prec, ns, nw, pass == 0 ? lsk::grad_waves_per_simd(ns, vps) : 0);
+            const int wps = pass == 0 ? lsk::grad_waves_per_simd(ns, vps)
+                                      : lsk::sweep_waves_per_simd(ns, lsk::sweep_slot_vgprs(vps, prior));
+            return shape_cost(N, prec, ns, nw, wps);
         };
         double best = 1e300;
         for (int nw = 1; nw <= lsk::kMaxWaves; ++nw)
@@ -305,8 +316,7 @@ extern "C" {
 
 size_t ls_model_workspace_bytes(int32_t N, int32_t L) {
     if (N < 2 || L < 1) return 0;
-    return emis_offset_bytes(N, L) + (size_t)L * (2 * sizeof(double) + 2 * sizeof(float)) +
-           (size_t)(L + 1) * sizeof(double);
+    return prior_stats_offset_bytes(N, L) + (size_t)N * 2 * sizeof(double);
 }
 
 ls_status ls_model_init(ls_model *m, void *workspace, size_t ws_bytes, void *stream) {
@@ -343,6 +353,22 @@ ls_status ls_model_init(ls_model *m, void *workspace, size_t ws_bytes, void *str
     h = fnv1a(h, &m->mu, sizeof m->mu);
     if (!rho.empty()) h = fnv1a(h, rho.data(), rho.size() * sizeof(double));
     if (!muv.empty()) h = fnv1a(h, muv.data(), muv.size() * sizeof(double));
+    if (m->prior) {
+        // every column in [0, 1] and summing to 1 off the diagonal; the
+        // per-column sums and checksums go into the hash
+        double *stats = reinterpret_cast<double *>(static_cast<char *>(workspace) +
+                                                   prior_stats_offset_bytes(m->N, m->L));
+        std::vector<double> hs((size_t)m->N * 2);
+        hipError_t e = lsk::launch_prior_stats(m->prior, m->N, stats, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hs.data(), stats, hs.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return LS_ERR_DEVICE;
+        for (int32_t c = 0; c < m->N; ++c)
+            if (!(std::fabs(hs[2 * (size_t)c] - 1.0) <= 1e-9)) return LS_ERR_ARG;
+        h = fnv1a(h, hs.data(), hs.size() * sizeof(double));
+    }
     if (h == 0) h = 1;
     const int64_t hs = hr_stride_for(m->N);
     uint64_t *Hr = static_cast<uint64_t *>(workspace);
@@ -436,7 +462,8 @@ ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t 
     }
     if (fwd->l == t) return T == 0 ? LS_OK : LS_ERR_ARG;
     Shape sh;
-    if (!choose_shape(m->N, fwd->prec, &sh)) return LS_ERR_UNSUPPORTED;
+    if (m->prior && (fwd->prec == LS_FP32_F16STORE || m->mu_vec)) return LS_ERR_UNSUPPORTED;
+    if (!choose_shape(m->N, fwd->prec, &sh, false, m->prior != nullptr)) return LS_ERR_UNSUPPORTED;
     SweepArgs a;
     std::memset(&a, 0, sizeof a);
     fill_scalars(a, m, fwd->prec, 0);
@@ -457,6 +484,7 @@ ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t 
     p.rho = m->L > 1 ? m->rho : reinterpret_cast<const double *>(m->Hr);  // only a discarded load when L == 1
     p.coef = coef_table(m, fwd->prec, 0);
     emission_tables(m, fwd->prec, p);
+    p.prior = m->prior;
     p.recipients = fwd->recipients;
     p.state = fwd->state;
     p.log_scale = fwd->log_scale;
@@ -492,7 +520,8 @@ ls_status ls_backward(ls_table *bck, const ls_model *m, int32_t t, const int32_t
     }
     if (bck->l == t) return T == 0 ? LS_OK : LS_ERR_ARG;
     Shape sh;
-    if (!choose_shape(m->N, bck->prec, &sh)) return LS_ERR_UNSUPPORTED;
+    if (m->prior && (bck->prec == LS_FP32_F16STORE || m->mu_vec)) return LS_ERR_UNSUPPORTED;
+    if (!choose_shape(m->N, bck->prec, &sh, false, m->prior != nullptr)) return LS_ERR_UNSUPPORTED;
     SweepArgs a;
     std::memset(&a, 0, sizeof a);
     fill_scalars(a, m, bck->prec, 1);
@@ -510,6 +539,7 @@ ls_status ls_backward(ls_table *bck, const ls_model *m, int32_t t, const int32_t
     p.rho = m->L > 1 ? m->rho : reinterpret_cast<const double *>(m->Hr);  // only a discarded load when L == 1
     p.coef = coef_table(m, bck->prec, 1);
     emission_tables(m, bck->prec, p);
+    p.prior = m->prior;
     p.recipients = bck->recipients;
     p.state = bck->state;
     p.log_scale = bck->log_scale;
@@ -591,6 +621,7 @@ ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R
     lsk::GradLayout lay;
     lsk::grad_workspace_bytes(m->N, m->L, R, (int)prec, muv, &lay);
     char *ws = static_cast<char *>(workspace);
+    if (grad && m->prior) return LS_ERR_UNSUPPORTED;  // the gradient takes the uniform prior
     hipStream_t st = as_stream(stream);
     const int32_t *rec = recipients;
     if (!rec) {

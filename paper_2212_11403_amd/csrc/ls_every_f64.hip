@@ -9,15 +9,16 @@ static hipError_t launch_every_one(const SweepPtrs &p, const SweepArgs &a, int n
                                    hipStream_t st) {
     using PT = PrecF64;
     if (nwaves < 1 || nwaves > max_waves_for(NSLOT, PT::vgpr_per_slot)) return hipErrorInvalidValue;
+    if (p.prior) return hipErrorInvalidValue;  // the gradient takes the uniform prior
     if (a.nblk < 1 || a.r0 < 0 || a.r0 + a.nblk > a.R) return hipErrorInvalidValue;
     if (p.emis)
         hipLaunchKernelGGL((sweep_kernel<PT, NSLOT, 0, true, true>), dim3(a.nblk),
                            dim3(64 * nwaves), 0, st, p.Hr, (const typename PT::T *)p.emis,
-                           p.lu_prefix, p.rho, p.coef, p.recipients, (typename PT::ST *)p.state,
+                           p.lu_prefix, nullptr, p.rho, p.coef, p.recipients, (typename PT::ST *)p.state,
                            p.log_scale, p.status, (typename PT::IO *)p.snap, a);
     else
         hipLaunchKernelGGL((sweep_kernel<PT, NSLOT, 0, true>), dim3(a.nblk), dim3(64 * nwaves), 0,
-                           st, p.Hr, nullptr, nullptr, p.rho, p.coef, p.recipients,
+                           st, p.Hr, nullptr, nullptr, nullptr, p.rho, p.coef, p.recipients,
                            (typename PT::ST *)p.state, p.log_scale, p.status,
                            (typename PT::IO *)p.snap, a);
     return hipGetLastError();

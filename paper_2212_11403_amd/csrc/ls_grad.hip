@@ -133,6 +133,7 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
         p.Hr = ga.Hr;
         p.emis = ga.emis;
         p.lu_prefix = ga.lu_prefix;
+        p.prior = nullptr;
         p.rho = ga.rho;
         p.coef = prec == 0 ? nullptr : ga.coef_fwd32;
         p.recipients = ga.recipients;

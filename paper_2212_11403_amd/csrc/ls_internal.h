@@ -25,6 +25,8 @@ struct SweepPtrs {
     const void *emis;           // per-variant mu: [L][2] emission pairs in the sweep's
                                 // arithmetic type, else null (scalar mu)
     const double *lu_prefix;    // per-variant mu, FP32 arithmetic: [L+1] log-unit prefix
+    const double *prior;        // prior copying matrix, [N][N] (row i: the prior
+                                // column of recipient i), or null (uniform)
     const double *rho;          // [L-1]
     const float *coef;          // [L][2] coefficient table of the precision and
                                 // direction (FP32 arithmetic), else null
@@ -86,12 +88,18 @@ struct Shape {
 // besides the resident vector (emission pair, accumulators, special-slot
 // multipliers, the division and reduction temporaries).
 __host__ __device__ constexpr int max_waves_for(int nslot, int vgpr_per_slot) {
-    int need = nslot * vgpr_per_slot + (vgpr_per_slot == 2 ? 64 : 44);
+    int need = nslot * vgpr_per_slot + (vgpr_per_slot >= 2 ? 64 : 44);
     need = (need + 7) / 8 * 8;
     int per_simd = 512 / need;
     if (per_simd > 8) per_simd = 8;
     int w = 4 * per_simd;
     return w > kMaxWaves ? kMaxWaves : (w < 1 ? 1 : w);
+}
+
+// Registers per slot of the sweep: the donor column and, with a prior
+// matrix, the prior column beside it.
+__host__ __device__ constexpr int sweep_slot_vgprs(int vgpr_per_slot, bool prior) {
+    return prior ? 2 * vgpr_per_slot : vgpr_per_slot;
 }
 
 // Largest group of the adjoint kernel that reads alpha ahead: per wave it
@@ -117,7 +125,7 @@ __host__ __device__ constexpr int grad_max_waves(int nslot, int vgpr_per_slot) {
 // otherwise spends registers on longer live ranges) and measured 6-10%
 // faster per sweep.
 __host__ __device__ constexpr int sweep_waves_per_simd(int nslot, int vgpr_per_slot) {
-    int need = nslot * vgpr_per_slot + (vgpr_per_slot == 2 ? 64 : 36);
+    int need = nslot * vgpr_per_slot + (vgpr_per_slot >= 2 ? 64 : 36);
     need = (need + 7) / 8 * 8;
     int w = 512 / need;
     return w > 8 ? 8 : (w < 1 ? 1 : w);
@@ -190,6 +198,11 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 // below l).
 hipError_t launch_emission_tables(const double *mu_vec, int32_t L, double *em64, float *em32,
                                   double *lu_prefix, hipStream_t st);
+// Per row i of a prior matrix ([N][N], row i = prior column of recipient i):
+// out[2i] = sum of the row without its diagonal (NaN if any entry is
+// negative, above 1 or not finite), out[2i+1] = sum_j (j+1) row[j] (a
+// checksum), both in a fixed order (ls_misc.hip).
+hipError_t launch_prior_stats(const double *prior, int32_t N, double *out, hipStream_t st);
 // Recombination map (eq. rho) and its chain rule (ls_misc.hip)
 hipError_t launch_calc_rho(const double *cM, int32_t n, double s, double gamma, double *rho,
                            hipStream_t st);

@@ -430,6 +430,46 @@ hipError_t launch_emission_tables(const double *mu_vec, int32_t L, double *em64,
 }
 
 // ---------------------------------------------------------------------------
+// Checks of a prior copying matrix (one workgroup per recipient's column):
+// strided per-thread sums in index order, then a fixed tree.
+__global__ void __launch_bounds__(256)
+prior_stats_kernel(const double *__restrict__ prior, int32_t N, double *__restrict__ out) {
+    __shared__ double ps[256], pw[256];
+    __shared__ int pbad[256];
+    const int i = blockIdx.x;
+    const double *row = prior + (int64_t)i * N;
+    double s = 0.0, w = 0.0;
+    int bad = 0;
+    for (int j = threadIdx.x; j < N; j += 256) {
+        const double x = row[j];
+        if (!(x >= 0.0 && x <= 1.0)) bad = 1;
+        if (j != i) s += x;
+        w += (double)(j + 1) * x;
+    }
+    ps[threadIdx.x] = s;
+    pw[threadIdx.x] = w;
+    pbad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            ps[threadIdx.x] += ps[threadIdx.x + h];
+            pw[threadIdx.x] += pw[threadIdx.x + h];
+            pbad[threadIdx.x] |= pbad[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * i] = pbad[0] ? __builtin_nan("") : ps[0];
+        out[2 * i + 1] = pw[0];
+    }
+}
+
+hipError_t launch_prior_stats(const double *prior, int32_t N, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(prior_stats_kernel, dim3(N), dim3(256), 0, st, prior, N, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Recombination map (eq. rho): rho_l = 1 - exp(-s m_l^gamma) with m_l =
 // cM_l / 100 the distance in Morgans (the argument is in centimorgans, as
 // the paper's CalcRho takes it), evaluated with expm1.

@@ -75,12 +75,22 @@ __device__ __forceinline__ SpecSlot special_slot(int q, int NF, int N, int g, bo
 // read from `emis` ([L][2], in the arithmetic type) and, in FP32 arithmetic,
 // the logs of the divisors of the pairs emitted by this launch are added to
 // the log scale from the prefix table `lu_prefix` ([L+1]).
-template <class PT, int NSLOT, int DIR, bool EVERY = false, bool MUV = false>
-__global__ void __launch_bounds__(64 * max_waves_for(NSLOT, PT::vgpr_per_slot))
+// PI: a prior copying matrix (section 2.1; eq. transition with Pi_ki in
+// place of 1/(N-1)). Row i of `prior` ([N][N] FP64) is the prior column of
+// recipient i; the kernel keeps pi' = (N-1) Pi_ji beside the donor column
+// (exactly 1 for the uniform prior). The forward jump term becomes b pi'_j,
+// and the backward normaliser the pi'-weighted column sum W' in place of S:
+// with y = theta^{l+1} (.) beta^{l+1}, beta^l is proportional to
+// (1 - rho_l) y / W + rho_l, W = sum_j Pi_ji y_j, so c = (1 - rho) kappa
+// (N-1) / W' and log G^l = log G^{l+1} + log(W' / ((N-1) kappa)).
+template <class PT, int NSLOT, int DIR, bool EVERY = false, bool MUV = false, bool PI = false>
+__global__ void __launch_bounds__(64 * max_waves_for(NSLOT, sweep_slot_vgprs(PT::vgpr_per_slot, PI)))
 __attribute__((amdgpu_waves_per_eu(
-    sweep_waves_per_simd(sweep_budget_slots(NSLOT, PT::vgpr_per_slot, EVERY), PT::vgpr_per_slot))))
+    sweep_waves_per_simd(sweep_budget_slots(NSLOT, sweep_slot_vgprs(PT::vgpr_per_slot, PI), EVERY),
+                         sweep_slot_vgprs(PT::vgpr_per_slot, PI)))))
 sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__ emis,
-             const double *__restrict__ lu_prefix, const double *__restrict__ rho,
+             const double *__restrict__ lu_prefix, const double *__restrict__ prior,
+             const double *__restrict__ rho,
              const float *__restrict__ coef, const int32_t *__restrict__ recipients, typename PT::ST *__restrict__ state,
              double *__restrict__ log_scale, uint32_t *__restrict__ status,
              typename PT::IO *__restrict__ snap, const SweepArgs a) {
@@ -93,7 +103,7 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
     using IO = typename PT::IO;
     constexpr int K = special_slots(NSLOT);
     constexpr int NR = NSLOT - K;
-    constexpr int MAXW = max_waves_for(NSLOT, PT::vgpr_per_slot);
+    constexpr int MAXW = max_waves_for(NSLOT, sweep_slot_vgprs(PT::vgpr_per_slot, PI));
     __shared__ T red[2 * kRedStride];
 
     const int nwaves = uniform(blockDim.x >> 6);
@@ -130,6 +140,31 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
     // the emission pair (match, mismatch), formed in FP64 by the host and
     // rounded once to the sweep precision
     const T th_m = (T)a.th_match, th_x = (T)a.th_mis;
+    // with a prior matrix: pi' = (N-1) Pi_ji per slot, 0 on the recipient's
+    // lane and on lanes without a donor
+    T pv[PI ? NSLOT : 1];
+    if constexpr (PI) {
+        const rsrc_t rs = make_rsrc(prior + (int64_t)i * N, (uint32_t)N * sizeof(double));
+        const int voff = lane * (int)sizeof(double);
+        const double n1 = (double)(N - 1);
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+            double x;
+            if (s < NR) {
+                int w = reg_base + s;
+                if (w >= NF) w -= NF;
+                x = buf_load<double>(rs, voff, w * 64 * (int)sizeof(double));
+                if (s == 0) x = lane_bit(m0) ? x : 0.0;
+            } else {
+                SpecSlot sp = special_slot(nwaves * NR + wave * K + (s - NR), NF, N, g, self_full,
+                                           sw, self_bit);
+                x = 0.0;
+                if (lane_bit(sp.bmask))
+                    x = buf_load<double>(rs, voff, sp.word * 64 * (int)sizeof(double));
+            }
+            pv[s] = (T)(x * n1);
+        }
+    }
 
     // resident vector in the arithmetic precision; the table state (ST) is
     // converted only when it is loaded or stored
@@ -177,6 +212,18 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
         else if (s & 1) acc1 += x;
         else acc0 += x;
     };
+    // the column sum a step hands on: the backward with a prior matrix sums
+    // pi' v (its normaliser W'), every other sweep v itself
+    auto account_sum = [&](int s, T x, T &acc0, T &acc1) __attribute__((always_inline)) {
+        if constexpr (PI && DIR == 1) {
+            if (s == 0) acc0 = pv[0] * x;
+            else if (s == 1) acc1 = pv[1] * x;
+            else if (s & 1) acc1 = fma(pv[s], x, acc1);
+            else acc0 = fma(pv[s], x, acc0);
+        } else {
+            accumulate(s, x, acc0, acc1);
+        }
+    };
     // Row words of slot s at variant row `row`.
     auto mask_of = [&](const uint64_t *row, int s) __attribute__((always_inline)) -> uint64_t {
         return (s < NR) ? row[reg_base + s] : row[spec_off[s - NR]];
@@ -192,10 +239,12 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
 #pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
             const T th = lane_bit(mask_of(row, s)) ? tb : ta;
-            const T bb = (s < NR) ? (s == 0 ? b * keep0 : b) : b * spec_keep[s - NR];
+            T bb;
+            if constexpr (PI && DIR == 0) bb = b * pv[s];
+            else bb = (s < NR) ? (s == 0 ? b * keep0 : b) : b * spec_keep[s - NR];
             const T nv = th * fma(c, (T)v[s], bb);
             v[s] = nv;
-            accumulate(s, nv, acc0, acc1);
+            account_sum(s, nv, acc0, acc1);
         }
         return acc0 + acc1;
     };
@@ -220,7 +269,7 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
             const T th = lane_bit(mask_of(row, s)) ? tb : ta;
             const T nv = th * v[s];
             v[s] = nv;
-            accumulate(s, nv, acc0, acc1);
+            account_sum(s, nv, acc0, acc1);
         }
         return acc0 + acc1;
     };

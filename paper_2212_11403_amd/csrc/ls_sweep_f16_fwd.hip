@@ -7,15 +7,16 @@ template <int NSLOT>
 static hipError_t launch_one(const SweepPtrs &p, const SweepArgs &a, int nwaves, hipStream_t st) {
     using PT = PrecF16;
     if (nwaves < 1 || nwaves > max_waves_for(NSLOT, PT::vgpr_per_slot)) return hipErrorInvalidValue;
+    if (p.prior) return hipErrorInvalidValue;  // no prior matrix with FP16 storage
     if (a.nblk < 1 || a.r0 < 0 || a.r0 + a.nblk > a.R) return hipErrorInvalidValue;
     if (p.emis)
         hipLaunchKernelGGL((sweep_kernel<PT, NSLOT, 0, false, true>), dim3(a.nblk),
-                           dim3(64 * nwaves), 0, st, p.Hr, (const PT::T *)p.emis, p.lu_prefix,
+                           dim3(64 * nwaves), 0, st, p.Hr, (const PT::T *)p.emis, p.lu_prefix, nullptr,
                            p.rho, p.coef, p.recipients, (PT::ST *)p.state, p.log_scale, p.status,
                            (PT::IO *)p.snap, a);
     else
         hipLaunchKernelGGL((sweep_kernel<PT, NSLOT, 0>), dim3(a.nblk), dim3(64 * nwaves), 0, st,
-                           p.Hr, nullptr, nullptr, p.rho, p.coef, p.recipients, (PT::ST *)p.state,
+                           p.Hr, nullptr, nullptr, nullptr, p.rho, p.coef, p.recipients, (PT::ST *)p.state,
                            p.log_scale, p.status, (PT::IO *)p.snap, a);
     return hipGetLastError();
 }

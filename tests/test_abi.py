@@ -47,7 +47,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_struct_layouts_match_header():
     from paper_2212_11403_amd._lib import LsModel, LsTable
-    assert ctypes.sizeof(LsModel) == 80
+    assert ctypes.sizeof(LsModel) == 88
     assert ctypes.sizeof(LsTable) == 56
 
 
@@ -62,8 +62,9 @@ def test_host_only_calls(lib):
     # (L FP64 pairs, L FP32 pairs, L + 1 FP64 prefix sums)
     def emis(L):
         return L * 16 + L * 8 + (L + 1) * 8
-    assert lib.ls_model_workspace_bytes(200, 10) == 768 + 4 * 10 * 2 * 4 + emis(10)
-    assert lib.ls_model_workspace_bytes(10000, 3) == 7680 + 4 * 3 * 2 * 4 + emis(3)
+    # and the [N][2] checks of a prior matrix
+    assert lib.ls_model_workspace_bytes(200, 10) == 768 + 4 * 10 * 2 * 4 + emis(10) + 16 * 200
+    assert lib.ls_model_workspace_bytes(10000, 3) == 7680 + 4 * 3 * 2 * 4 + emis(3) + 16 * 10000
 
 
 def test_validation_errors_before_any_device_work(lib):
