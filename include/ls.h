@@ -110,10 +110,11 @@ typedef struct {
                              used: self copying is excluded), else
                              ls_model_init returns LS_ERR_ARG. NULL: the
                              uniform prior 1/(N-1). Used by decoding and the
-                             log-likelihood in LS_FP64 and LS_FP32 with a
-                             scalar mu; other uses return
-                             LS_ERR_UNSUPPORTED. The caller keeps it alive
-                             and unchanged while the model is in use. */
+                             log-likelihood in every precision, with a
+                             scalar mu or mu_vec; the gradient returns
+                             LS_ERR_UNSUPPORTED for such a model. The
+                             caller keeps it alive and unchanged while the
+                             model is in use. */
 } ls_model;
 
 /* Device bytes of the workspace ls_model_init lays the internal haplotype

@@ -462,7 +462,6 @@ ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t 
     }
     if (fwd->l == t) return T == 0 ? LS_OK : LS_ERR_ARG;
     Shape sh;
-    if (m->prior && (fwd->prec == LS_FP32_F16STORE || m->mu_vec)) return LS_ERR_UNSUPPORTED;
     if (!choose_shape(m->N, fwd->prec, &sh, false, m->prior != nullptr)) return LS_ERR_UNSUPPORTED;
     SweepArgs a;
     std::memset(&a, 0, sizeof a);
@@ -520,7 +519,6 @@ ls_status ls_backward(ls_table *bck, const ls_model *m, int32_t t, const int32_t
     }
     if (bck->l == t) return T == 0 ? LS_OK : LS_ERR_ARG;
     Shape sh;
-    if (m->prior && (bck->prec == LS_FP32_F16STORE || m->mu_vec)) return LS_ERR_UNSUPPORTED;
     if (!choose_shape(m->N, bck->prec, &sh, false, m->prior != nullptr)) return LS_ERR_UNSUPPORTED;
     SweepArgs a;
     std::memset(&a, 0, sizeof a);

@@ -196,8 +196,11 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
     auto thetas = [&](uint64_t sw_bits, T em, T ex, T &ta, T &tb) __attribute__((always_inline)) {
         const bool rb = (sw_bits & self_bit) != 0;
         if constexpr (MUV) {
-            ta = rb ? ex : em;
-            tb = rb ? em : ex;
+            // kept in VGPRs: as a select of two loaded scalars the compiler
+            // flips every row mask with a scalar xor instead (one more
+            // instruction per slot)
+            ta = in_vgpr(rb ? ex : em);
+            tb = in_vgpr(rb ? em : ex);
         } else {
             ta = rb ? th_x : th_m;
             tb = rb ? th_m : th_x;

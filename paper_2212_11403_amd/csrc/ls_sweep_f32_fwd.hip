@@ -9,13 +9,17 @@ static hipError_t launch_one(const SweepPtrs &p, const SweepArgs &a, int nwaves,
     const int vps = sweep_slot_vgprs(PT::vgpr_per_slot, p.prior != nullptr);
     if (nwaves < 1 || nwaves > max_waves_for(NSLOT, vps)) return hipErrorInvalidValue;
     if (a.nblk < 1 || a.r0 < 0 || a.r0 + a.nblk > a.R) return hipErrorInvalidValue;
-    if (p.prior) {
-        if (p.emis) return hipErrorInvalidValue;  // not with a per-variant mu
+    if (p.prior && p.emis)
+        hipLaunchKernelGGL((sweep_kernel<PT, NSLOT, 0, false, true, true>), dim3(a.nblk),
+                           dim3(64 * nwaves), 0, st, p.Hr, (const PT::T *)p.emis, p.lu_prefix,
+                           p.prior, p.rho, p.coef, p.recipients, (PT::ST *)p.state, p.log_scale,
+                           p.status, (PT::IO *)p.snap, a);
+    else if (p.prior)
         hipLaunchKernelGGL((sweep_kernel<PT, NSLOT, 0, false, false, true>), dim3(a.nblk),
                            dim3(64 * nwaves), 0, st, p.Hr, nullptr, nullptr, p.prior, p.rho,
                            p.coef, p.recipients, (PT::ST *)p.state, p.log_scale, p.status,
                            (PT::IO *)p.snap, a);
-    } else if (p.emis)
+    else if (p.emis)
         hipLaunchKernelGGL((sweep_kernel<PT, NSLOT, 0, false, true>), dim3(a.nblk),
                            dim3(64 * nwaves), 0, st, p.Hr, (const PT::T *)p.emis, p.lu_prefix, nullptr,
                            p.rho, p.coef, p.recipients, (PT::ST *)p.state, p.log_scale, p.status,

@@ -18,6 +18,13 @@
                          (N = 100,000, L = 10,000, 5 targets): recipients
                          [0, 12,500) against all 100,000 donors, FP32 decode
                          time, E-write bandwidth, posterior error vs the oracle
+    python study.py c2var  the benchmark workload's decode step (N = 10,000,
+                         L = 100,000, 100 targets, all recipients, FP32) with a
+                         scalar mu, a per-variant mu (log-uniform within a
+                         decade of the workload's mu) and a skewed prior
+                         matrix Pi: decode time of each and its posteriors
+                         and log-likelihoods vs the oracle on seeded
+                         recipients
     python study.py emu  (CPU only) numpy emulation of the FP32 forward sweep
                          against the same recursion in FP64, with the column
                          sum taken in the kernel's order, with Kahan lane sums
@@ -506,9 +513,57 @@ def study_emu(args):
     print(json.dumps(out), flush=True)
 
 
+def study_c2var(args):
+    import torch
+
+    import oracle
+    import paper_2212_11403_amd as ls
+    from lsinputs import make_inputs, seeded_recipients
+
+    x = make_inputs("c2")
+    N, L, targets = x["N"], x["L"], x["targets"]
+    rng = np.random.default_rng(2212)
+    mu_vec = x["mu"] * 10.0 ** rng.uniform(-1.0, 1.0, L)
+    W = rng.random((N, N)) ** 3
+    np.fill_diagonal(W, 0.0)
+    Pi = W / W.sum(axis=0, keepdims=True)
+    del W
+    rec = seeded_recipients(N, args.recipients, seed=22)
+    out = {"study": "c2 variants (FP32 decode)", "N": N, "L": L, "targets": len(targets),
+           "oracle_recipients": len(rec)}
+    variants = [("scalar_mu", x["mu"], None), ("vector_mu", mu_vec, None),
+                ("prior_matrix", x["mu"], Pi)]
+    for name, mu, prior in variants:
+        model = ls.Model(x["H"], N, x["rho"], mu, prior=prior)
+        ls.decode(model, targets[:1], "fp32", want=("E",))  # warm-up
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = ls.decode(model, targets, "fp32", want=("E",))
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t1
+        del r
+        res = {"decode_seconds": sec, "cells_per_s": float(N) * N * L / sec}
+        t0 = time.perf_counter()
+        ref = oracle.run_pass(x["H"], N, L, x["rho"], mu, rec, targets, want=("P",), prior=prior)
+        res["oracle_seconds"] = time.perf_counter() - t0
+        g = ls.decode(model, targets, "fp32", recipients=rec, want=("P",))
+        res["max_posterior_err_vs_oracle"] = float(np.abs(g["P"].double().cpu().numpy()
+                                                          - ref["P"]).max())
+        ll = g["fwd"].log_scale.cpu().numpy()
+        res["max_rel_loglik_err_vs_oracle"] = float(np.max(np.abs(ll - ref["llf"])
+                                                           / np.abs(ref["llf"])))
+        out[name] = res
+        log(f"{name}: {res}")
+        del model, g
+        torch.cuda.empty_cache()
+    out["vector_mu_time_ratio"] = out["vector_mu"]["decode_seconds"] / out["scalar_mu"]["decode_seconds"]
+    out["prior_time_ratio"] = out["prior_matrix"]["decode_seconds"] / out["scalar_mu"]["decode_seconds"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c2", "c3", "c4", "c5", "emu"])
+    ap.add_argument("which", choices=["c2", "c3", "c4", "c5", "c2var", "emu"])
     ap.add_argument("--recipients", type=int, default=None,
                     help="seeded recipients checked against the oracle")
     ap.add_argument("--fd", type=int, default=64, help="finite-difference components (c4)")
@@ -531,6 +586,9 @@ def main():
     elif args.which == "c4":
         args.recipients = args.recipients or 2000
         study_c4(args)
+    elif args.which == "c2var":
+        args.recipients = args.recipients or 16
+        study_c2var(args)
     elif args.which == "c3":
         args.recipients = args.recipients or 256
         study_c3(args)

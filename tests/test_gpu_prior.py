@@ -133,20 +133,34 @@ def test_prior_loglik(ls, prec):
     _check(prec, _np(out["loglik"]), ref["llf"], "log")
 
 
+@pytest.mark.parametrize("N,L", [(65, 40), (1031, 12), (200, 3000)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "f16"])
+def test_prior_with_vector_mu_matches_oracle(ls, N, L, prec):
+    """A prior matrix together with a per-variant mu (mu over four decades,
+    some above 1/2); FP16 storage also with the prior alone."""
+    H, rho, _, Pi = _case(N, L, seed=N + 11 * L)
+    rng = np.random.default_rng(N + L)
+    mu = 10.0 ** rng.uniform(-5, -1, L)
+    mu[rng.random(L) < 0.1] = 0.6
+    targets = np.unique(np.array([0, L // 2, L - 1], np.int32))
+    rec = np.arange(N, dtype=np.int32) if N <= 300 else np.array([0, 64, N - 1], np.int32)
+    for m_arg in ((mu, 0.01) if prec == "f16" else (mu,)):
+        ref = oracle.run_pass(H, N, L, rho, m_arg, rec, targets, want=("P", "logG"), prior=Pi)
+        m = ls.Model(H, N, rho, m_arg, prior=Pi)
+        r = ls.decode(m, targets, prec, recipients=rec, want=("P",))
+        assert ls.status_check(r["fwd"]) == ls.LS_OK
+        _check(prec, _np(r["P"]), ref["P"], "prob")
+        _check(prec, _np(r["fwd"].log_scale), ref["llf"], "log")
+        _check(prec, _np(r["bck"].log_scale), ref["logG"][0], "log")
+
+
 def test_prior_unsupported_and_invalid(ls):
     N, L = 70, 10
     H, rho, mu, Pi = _case(N, L, seed=4)
     m = ls.Model(H, N, rho, mu, prior=Pi)
     with pytest.raises(ls.LsError) as e:
-        ls.decode(m, [3], "f16", want=("P",))
-    assert e.value.code == 4  # LS_ERR_UNSUPPORTED
-    with pytest.raises(ls.LsError) as e:
         ls.loglik_grad(m, prec="fp64", grad=True)
-    assert e.value.code == 4
-    mv = ls.Model(H, N, rho, np.full(L, mu), prior=Pi)
-    with pytest.raises(ls.LsError) as e:
-        ls.decode(mv, [3], "fp32", want=("P",))
-    assert e.value.code == 4
+    assert e.value.code == 4  # LS_ERR_UNSUPPORTED
     with pytest.raises(ValueError):
         ls.Model(H, N, rho, mu, prior=Pi[:-1])
     bad = Pi.copy()
