@@ -142,9 +142,11 @@ grad_seg_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
         const uint64_t flip = rb ? ~0ull : 0ull;
         T ta, tb;
         if constexpr (MUV) {
+            // kept in VGPRs, as in the sweep (else the row masks are flipped
+            // with scalar xors)
             const T em = emis[2 * ll], ex = emis[2 * ll + 1];
-            ta = rb ? ex : em;
-            tb = rb ? em : ex;
+            ta = in_vgpr(rb ? ex : em);
+            tb = in_vgpr(rb ? em : ex);
         } else {
             ta = rb ? th_x : th_m;
             tb = rb ? th_m : th_x;

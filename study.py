@@ -25,6 +25,11 @@
                          matrix Pi: decode time of each and its posteriors
                          and log-likelihoods vs the oracle on seeded
                          recipients
+    python study.py c4var  the gradient workload (N = 2,000, L = 50,000) with a
+                         scalar and with a per-variant mu (log-uniform within
+                         a decade of the workload's mu): time per gradient in
+                         FP32 and FP64, and the gradient vs the oracle score
+                         on seeded recipients
     python study.py emu  (CPU only) numpy emulation of the FP32 forward sweep
                          against the same recursion in FP64, with the column
                          sum taken in the kernel's order, with Kahan lane sums
@@ -561,9 +566,55 @@ def study_c2var(args):
     print(json.dumps(out), flush=True)
 
 
+def study_c4var(args):
+    import torch
+
+    import oracle
+    import paper_2212_11403_amd as ls
+    from lsinputs import make_inputs, seeded_recipients
+
+    x = make_inputs("c4")
+    N, L = x["N"], x["L"]
+    mu_vec = x["mu"] * 10.0 ** np.random.default_rng(4).uniform(-1.0, 1.0, L)
+    rec = seeded_recipients(N, args.recipients, seed=44)
+    out = {"study": "c4 gradient with a per-variant mu", "N": N, "L": L,
+           "oracle_recipients": len(rec)}
+    for name, mu in (("scalar_mu", x["mu"]), ("vector_mu", mu_vec)):
+        model = ls.Model(x["H"], N, x["rho"], mu)
+        t0 = time.perf_counter()
+        ref = oracle.run_gradient(x["H"], N, L, x["rho"], mu, rec)
+        res = {"oracle_seconds": time.perf_counter() - t0}
+        for prec in ("fp32", "fp64"):
+            ls.loglik_grad(model, None, prec, grad=True)  # warm-up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            reps = 3
+            for _ in range(reps):
+                ls.loglik_grad(model, None, prec, grad=True)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t1) / reps * 1e3
+            g = ls.loglik_grad(model, rec, prec, grad=True)
+            gr = g["grad_rho"].cpu().numpy()
+            rr = ref["grad_rho"].sum(axis=0)
+            gm = g["grad_mu"].cpu().numpy()
+            rm = ref["grad_mu_l"].sum(axis=0) if "grad_mu_l" in ref else ref["grad_mu"].sum()
+            res[prec] = {"ms_per_gradient": ms,
+                         "rho_err_normwise": float(np.abs(gr - rr).max() / np.abs(rr).max()),
+                         "mu_err_normwise": float(np.max(np.abs(gm - rm)) / np.max(np.abs(rm))),
+                         "pac_rel_err": float(abs(g["pac"].item() - ref["loglik"].sum())
+                                              / abs(ref["loglik"].sum()))}
+        out[name] = res
+        log(f"{name}: {res}")
+    out["vector_mu_time_ratio_fp32"] = (out["vector_mu"]["fp32"]["ms_per_gradient"]
+                                        / out["scalar_mu"]["fp32"]["ms_per_gradient"])
+    out["vector_mu_time_ratio_fp64"] = (out["vector_mu"]["fp64"]["ms_per_gradient"]
+                                        / out["scalar_mu"]["fp64"]["ms_per_gradient"])
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c2", "c3", "c4", "c5", "c2var", "emu"])
+    ap.add_argument("which", choices=["c2", "c3", "c4", "c5", "c2var", "c4var", "emu"])
     ap.add_argument("--recipients", type=int, default=None,
                     help="seeded recipients checked against the oracle")
     ap.add_argument("--fd", type=int, default=64, help="finite-difference components (c4)")
@@ -586,6 +637,9 @@ def main():
     elif args.which == "c4":
         args.recipients = args.recipients or 2000
         study_c4(args)
+    elif args.which == "c4var":
+        args.recipients = args.recipients or 32
+        study_c4var(args)
     elif args.which == "c2var":
         args.recipients = args.recipients or 16
         study_c2var(args)
