@@ -182,3 +182,30 @@ def test_prior_unsupported_and_invalid(ls):
     with pytest.raises(ls.LsError) as e:
         ls.forward(t, m2, 5)
     assert e.value.code == 3  # LS_ERR_STATE
+
+
+PRIOR_SHAPES = [  # (precision, N, slots, waves): multi-wave layouts and special slots
+    ("fp64", 700, 4, 3), ("fp64", 1031, 4, 5), ("fp64", 333, 1, 6), ("fp64", 4160, 16, 5),
+    ("fp32", 700, 3, 4), ("fp32", 1031, 12, 2), ("fp32", 4160, 12, 6),
+]
+
+
+@pytest.mark.parametrize("prec,N,ns,nw", PRIOR_SHAPES)
+def test_prior_forced_shapes(ls, prec, N, ns, nw):
+    """Group shapes chosen by hand (each must fit the doubled per-slot
+    registers of the prior column): every lane of every slot class holds
+    the right prior entry."""
+    from _gpu import forced_shape
+    L = 9
+    H, rho, mu, Pi = _case(N, L, seed=N + 3 * ns + nw)
+    targets = np.array([0, 2, 5], np.int32)  # the backward table ends at variant 0
+    rec = np.array(sorted({0, 1, 63, 64, N // 2, N - 2, N - 1}), dtype=np.int32)
+    ref = oracle.run_pass(H, N, L, rho, mu, rec, targets, want=("P", "B", "logG"), prior=Pi)
+    m = ls.Model(H, N, rho, mu, prior=Pi)
+    with forced_shape(ns, nw):
+        r = ls.decode(m, targets, prec, recipients=rec, want=("P",))
+    _check(prec, _np(r["P"]), ref["P"], "prob")
+    _check(prec, _np(r["fwd"].log_scale), ref["llf"], "log")
+    _check(prec, _np(r["bck"].log_scale), ref["logG"][0], "log")
+    if prec == "fp64":
+        rel_close(_np(r["bsnap"]), ref["B"], F64_RTOL, F64_ATOL_PROB)
