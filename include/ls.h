@@ -109,12 +109,11 @@ typedef struct {
                              summing to 1 without its diagonal (which is not
                              used: self copying is excluded), else
                              ls_model_init returns LS_ERR_ARG. NULL: the
-                             uniform prior 1/(N-1). Used by decoding and the
-                             log-likelihood in every precision, with a
-                             scalar mu or mu_vec; the gradient returns
-                             LS_ERR_UNSUPPORTED for such a model. The
-                             caller keeps it alive and unchanged while the
-                             model is in use. */
+                             uniform prior 1/(N-1). Used by decoding, the
+                             log-likelihood and its gradient, with a scalar
+                             mu or mu_vec, in every precision that offers
+                             them. The caller keeps it alive and unchanged
+                             while the model is in use. */
 } ls_model;
 
 /* Device bytes of the workspace ls_model_init lays the internal haplotype

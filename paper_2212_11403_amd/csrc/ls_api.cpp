@@ -139,10 +139,10 @@ bool choose_shape(int32_t N, int prec, Shape *out, bool grad = false, bool prior
     for (int pass = grad ? 0 : 1; pass < 2; ++pass) {
         auto ok = [&](int ns, int nw) {
             return shape_fits(N, prec, ns, nw, prior) &&
-                   (pass == 1 || nw <= lsk::grad_max_waves(ns, vps));
+                   (pass == 1 || nw <= lsk::grad_max_waves(ns, vps, prior));
         };
         auto cost = [&](int ns, int nw) {
-            const int wps = pass == 0 ? lsk::grad_waves_per_simd(ns, vps)
+            const int wps = pass == 0 ? lsk::grad_waves_per_simd(ns, vps, prior)
                                       : lsk::sweep_waves_per_simd(ns, lsk::sweep_slot_vgprs(vps, prior));
             return shape_cost(N, prec, ns, nw, wps);
         };
@@ -615,11 +615,10 @@ ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R
     if (!workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
         return LS_ERR_WORKSPACE;
     Shape sh;
-    if (!choose_shape(m->N, prec, &sh, grad)) return LS_ERR_UNSUPPORTED;
+    if (!choose_shape(m->N, prec, &sh, grad, m->prior != nullptr)) return LS_ERR_UNSUPPORTED;
     lsk::GradLayout lay;
     lsk::grad_workspace_bytes(m->N, m->L, R, (int)prec, muv, &lay);
     char *ws = static_cast<char *>(workspace);
-    if (grad && m->prior) return LS_ERR_UNSUPPORTED;  // the gradient takes the uniform prior
     hipStream_t st = as_stream(stream);
     const int32_t *rec = recipients;
     if (!rec) {
@@ -665,7 +664,9 @@ ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R
         ga.em64 = static_cast<const double *>(e64.emis);
     }
     ga.chunk = sweep_chunk();
-    if (!choose_shape(m->N, prec, &ga.fwd_shape)) return LS_ERR_UNSUPPORTED;
+    if (!choose_shape(m->N, prec, &ga.fwd_shape, false, m->prior != nullptr))
+        return LS_ERR_UNSUPPORTED;
+    ga.prior = m->prior;
     ga.ws = ws;
     ga.lay = lay;
     return dev(lsk::launch_grad(ga, (int)prec, sh, loglik, pac, grad_rho, grad_mu, st));

@@ -8,10 +8,21 @@ template <int NSLOT>
 static hipError_t launch_every_one(const SweepPtrs &p, const SweepArgs &a, int nwaves,
                                    hipStream_t st) {
     using PT = PrecF32;
-    if (nwaves < 1 || nwaves > max_waves_for(NSLOT, PT::vgpr_per_slot)) return hipErrorInvalidValue;
-    if (p.prior) return hipErrorInvalidValue;  // the gradient takes the uniform prior
+    const int vps = sweep_slot_vgprs(PT::vgpr_per_slot, p.prior != nullptr);
+    if (nwaves < 1 || nwaves > max_waves_for(NSLOT, vps)) return hipErrorInvalidValue;
     if (a.nblk < 1 || a.r0 < 0 || a.r0 + a.nblk > a.R) return hipErrorInvalidValue;
-    if (p.emis)
+    if (p.emis && p.prior)
+        hipLaunchKernelGGL((sweep_kernel<PT, NSLOT, 0, true, true, true>), dim3(a.nblk),
+                           dim3(64 * nwaves), 0, st, p.Hr, (const typename PT::T *)p.emis,
+                           p.lu_prefix, p.prior, p.rho, p.coef, p.recipients,
+                           (typename PT::ST *)p.state, p.log_scale, p.status,
+                           (typename PT::IO *)p.snap, a);
+    else if (p.prior)
+        hipLaunchKernelGGL((sweep_kernel<PT, NSLOT, 0, true, false, true>), dim3(a.nblk),
+                           dim3(64 * nwaves), 0, st, p.Hr, nullptr, nullptr, p.prior, p.rho,
+                           p.coef, p.recipients, (typename PT::ST *)p.state, p.log_scale,
+                           p.status, (typename PT::IO *)p.snap, a);
+    else if (p.emis)
         hipLaunchKernelGGL((sweep_kernel<PT, NSLOT, 0, true, true>), dim3(a.nblk),
                            dim3(64 * nwaves), 0, st, p.Hr, (const typename PT::T *)p.emis,
                            p.lu_prefix, nullptr, p.rho, p.coef, p.recipients, (typename PT::ST *)p.state,

@@ -95,7 +95,7 @@ hipError_t launch_loglik_sum(const double *ll, int32_t R, double *loglik, double
 static hipError_t dispatch_grad_seg(int prec, const GradArgs &ga, const GradSegArgs &sa, Shape sh,
                                     hipStream_t st) {
     const int vps = prec == 0 ? 2 : 1;
-    const bool narrow = sh.nwaves <= grad_max_waves(sh.nslot, vps);
+    const bool narrow = sh.nwaves <= grad_max_waves(sh.nslot, vps, ga.prior != nullptr);
     if (prec == 0)
         return narrow ? grad_seg_f64_narrow(ga, sa, sh, st) : grad_seg_f64_wide(ga, sa, sh, st);
     return narrow ? grad_seg_f32_narrow(ga, sa, sh, st) : grad_seg_f32_wide(ga, sa, sh, st);
@@ -133,7 +133,7 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
         p.Hr = ga.Hr;
         p.emis = ga.emis;
         p.lu_prefix = ga.lu_prefix;
-        p.prior = nullptr;
+        p.prior = ga.prior;
         p.rho = ga.rho;
         p.coef = prec == 0 ? nullptr : ga.coef_fwd32;
         p.recipients = ga.recipients;

@@ -24,6 +24,10 @@ namespace lsk {
 //   M_l = sum_{j mismatching at l} alpha^l_j beta^l_j / sum_j alpha^l_j beta^l_j
 //   d log P / d mu += M_l / mu - (1 - M_l) / (1 - mu).
 // Per-variant rho terms go to grow[l][r]; the mu term accumulates in gmu[r].
+// PI (a prior copying matrix): the kernel keeps pi' = (N-1) Pi_ji beside
+// y, as the sweep does; Sy becomes the pi'-weighted sum W' (so c =
+// (1 - rho)(N-1) / W' and pi Sa Sy = Sa sum_j Pi_ji y_j, the prior-weighted
+// normaliser of the score), and the derived forward step adds b pi'_j.
 // MUV (a mutation probability per variant): theta^l is the pair of variant
 // l from `emis` (the sweep's table), and d log P / d mu^l = M_l / mu^l -
 // (1 - M_l) / (1 - mu^l), with the FP64 pair from `em64`, goes to
@@ -52,14 +56,16 @@ struct GradSegArgs {
 // 16-wave groups of the largest N (at the price of register spills).
 // (A slot count with no narrow shape still instantiates the narrow kernel,
 // with a 4-wave bound, but never launches it.)
-__host__ __device__ constexpr int grad_kernel_waves(int nslot, int vgpr_per_slot, bool narrow) {
-    return !narrow ? max_waves_for(nslot, vgpr_per_slot)
-                   : (grad_max_waves(nslot, vgpr_per_slot) > 0 ? grad_max_waves(nslot, vgpr_per_slot)
-                                                                : 4);
+__host__ __device__ constexpr int grad_kernel_waves(int nslot, int vgpr_per_slot, bool narrow,
+                                                    bool prior = false) {
+    return !narrow ? max_waves_for(nslot, sweep_slot_vgprs(vgpr_per_slot, prior))
+                   : (grad_max_waves(nslot, vgpr_per_slot, prior) > 0
+                          ? grad_max_waves(nslot, vgpr_per_slot, prior)
+                          : 4);
 }
 
-template <class PT, int NSLOT, bool NARROW, bool MUV = false>
-__global__ void __launch_bounds__(64 * grad_kernel_waves(NSLOT, PT::vgpr_per_slot, NARROW))
+template <class PT, int NSLOT, bool NARROW, bool MUV = false, bool PI = false>
+__global__ void __launch_bounds__(64 * grad_kernel_waves(NSLOT, PT::vgpr_per_slot, NARROW, PI))
 grad_seg_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
                 const float *__restrict__ coef, const float *__restrict__ coefb,
                 const int32_t *__restrict__ recipients,
@@ -67,12 +73,13 @@ grad_seg_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
                 const typename PT::T *__restrict__ cval, typename PT::T *__restrict__ ybuf,
                 double *__restrict__ grow, double *__restrict__ gmu,
                 const typename PT::T *__restrict__ emis, const double *__restrict__ em64,
-                double *__restrict__ gmul, const GradSegArgs a) {
+                double *__restrict__ gmul, const double *__restrict__ prior,
+                const GradSegArgs a) {
 #pragma clang fp contract(off)
     using T = typename PT::T;
     constexpr int K = special_slots(NSLOT);
     constexpr int NR = NSLOT - K;
-    constexpr int MAXW = grad_kernel_waves(NSLOT, PT::vgpr_per_slot, NARROW);
+    constexpr int MAXW = grad_kernel_waves(NSLOT, PT::vgpr_per_slot, NARROW, PI);
     __shared__ T red[2 * kRedStride];
 
     const int nwaves = uniform(blockDim.x >> 6);
@@ -112,6 +119,24 @@ grad_seg_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
         return w >= NF ? w - NF : w;
     };
 
+    // with a prior matrix: pi' = (N-1) Pi_ji per slot, 0 on the recipient's
+    // lane and on lanes without a donor (those read element 0, then masked)
+    T pv[PI ? NSLOT : 1];
+    if constexpr (PI) {
+        const double *prow = prior + (int64_t)i * N;
+        const double n1 = (double)(N - 1);
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+            double x;
+            if (s < NR) {
+                x = prow[word_of(s) * 64 + lane];
+                if (s == 0) x = lane_bit(m0) ? x : 0.0;
+            } else {
+                x = prow[spec_voff[s - NR]] * (double)spec_keep[s - NR];
+            }
+            pv[s] = (T)(x * n1);
+        }
+    }
     T y[NSLOT];
     double gm = 0.0;
     T Sy = (T)0;
@@ -158,7 +183,9 @@ grad_seg_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
             const T th = lane_bit(m) ? tb : ta;
             T al = src[s];
             if constexpr (DERIVE) {
-                const T bbf = (s < NR) ? (s == 0 ? bf * keep0 : bf) : bf * spec_keep[s - NR];
+                T bbf;
+            if constexpr (PI) bbf = bf * pv[s];
+            else bbf = (s < NR) ? (s == 0 ? bf * keep0 : bf) : bf * spec_keep[s - NR];
                 al = th * fma(cf, al, bbf);
             }
             if (s >= NR) al = al * spec_keep[s - NR];
@@ -169,7 +196,8 @@ grad_seg_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
             mn = fma(lane_bit(m ^ flip) ? al : (T)0, u, mn);
             const T nv = th * u;
             y[s] = nv;
-            sy += nv;
+            if constexpr (PI) sy = fma(pv[s], nv, sy);
+            else sy += nv;
         }
         out[0] = d;
         out[1] = sa;
@@ -269,7 +297,8 @@ grad_seg_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
                 x = buf_load<T>(rs, spec_voff[s - NR] * (int)sizeof(T), 0) * spec_keep[s - NR];
             }
             y[s] = x;
-            sy += x;
+            if constexpr (PI) sy = fma(pv[s], x, sy);
+            else sy += x;
         }
         T q[4] = {sy, (T)0, (T)0, (T)0};
         block_sum4<MAXW>(q, red, parity, wave);
@@ -324,7 +353,7 @@ grad_seg_kernel(const uint64_t *__restrict__ Hr, const double *__restrict__ rho,
 template <class PT, int NSLOT, bool NARROW>
 hipError_t launch_grad_seg(const GradArgs &ga, const GradSegArgs &sa, int nwaves, hipStream_t st) {
     using T = typename PT::T;
-    if (nwaves < 1 || nwaves > grad_kernel_waves(NSLOT, PT::vgpr_per_slot, NARROW))
+    if (nwaves < 1 || nwaves > grad_kernel_waves(NSLOT, PT::vgpr_per_slot, NARROW, ga.prior != nullptr))
         return hipErrorInvalidValue;
     const GradLayout &L = ga.lay;
     char *ws = ga.ws;
@@ -337,16 +366,25 @@ hipError_t launch_grad_seg(const GradArgs &ga, const GradSegArgs &sa, int nwaves
     double *gmu = reinterpret_cast<double *>(ws + L.off_gmu);
     const float *coef = sizeof(T) == 4 ? ga.coef_fwd32 : nullptr;
     const float *coefb = sizeof(T) == 4 ? ga.coef_bwd32 : nullptr;
-    if (ga.emis)
+    const T *emis = reinterpret_cast<const T *>(ga.emis);
+    double *gmul = reinterpret_cast<double *>(ws + L.off_gmul);
+    if (ga.emis && ga.prior)
+        hipLaunchKernelGGL((grad_seg_kernel<PT, NSLOT, NARROW, true, true>), dim3(ga.R),
+                           dim3(64 * nwaves), 0, st, ga.Hr, ga.rho, coef, coefb, ga.recipients,
+                           alpha0, aseg, cval, ybuf, grow, gmu, emis, ga.em64, gmul, ga.prior, sa);
+    else if (ga.prior)
+        hipLaunchKernelGGL((grad_seg_kernel<PT, NSLOT, NARROW, false, true>), dim3(ga.R),
+                           dim3(64 * nwaves), 0, st, ga.Hr, ga.rho, coef, coefb, ga.recipients,
+                           alpha0, aseg, cval, ybuf, grow, gmu, nullptr, nullptr, nullptr,
+                           ga.prior, sa);
+    else if (ga.emis)
         hipLaunchKernelGGL((grad_seg_kernel<PT, NSLOT, NARROW, true>), dim3(ga.R),
                            dim3(64 * nwaves), 0, st, ga.Hr, ga.rho, coef, coefb, ga.recipients,
-                           alpha0, aseg, cval, ybuf, grow, gmu,
-                           reinterpret_cast<const T *>(ga.emis), ga.em64,
-                           reinterpret_cast<double *>(ws + L.off_gmul), sa);
+                           alpha0, aseg, cval, ybuf, grow, gmu, emis, ga.em64, gmul, nullptr, sa);
     else
         hipLaunchKernelGGL((grad_seg_kernel<PT, NSLOT, NARROW>), dim3(ga.R), dim3(64 * nwaves), 0,
                            st, ga.Hr, ga.rho, coef, coefb, ga.recipients, alpha0, aseg, cval, ybuf,
-                           grow, gmu, nullptr, nullptr, nullptr, sa);
+                           grow, gmu, nullptr, nullptr, nullptr, nullptr, sa);
     return hipGetLastError();
 }
 
@@ -354,7 +392,9 @@ hipError_t launch_grad_seg(const GradArgs &ga, const GradSegArgs &sa, int nwaves
 // narrow one allows.
 template <class PT, int NSLOT>
 constexpr bool grad_wide_needed() {
-    return grad_max_waves(NSLOT, PT::vgpr_per_slot) < max_waves_for(NSLOT, PT::vgpr_per_slot);
+    constexpr int v = PT::vgpr_per_slot;
+    return grad_max_waves(NSLOT, v) < max_waves_for(NSLOT, v) ||
+           grad_max_waves(NSLOT, v, true) < max_waves_for(NSLOT, sweep_slot_vgprs(v, true));
 }
 
 // Adjoint launchers over the slot menu, one per precision and variant

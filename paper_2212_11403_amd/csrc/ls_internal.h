@@ -106,15 +106,18 @@ __host__ __device__ constexpr int sweep_slot_vgprs(int vgpr_per_slot, bool prior
 // holds y, the alpha of the current pair of variants and of the next, and
 // the temporaries of two steps; 7 registers per slot plus 28 (FP32), 14.5
 // per slot plus 40 (FP64), fitted to the compiler's allocations, so that
-// the occupancy the shape choice assumes is the one the kernel gets.
-__host__ __device__ constexpr int grad_waves_per_simd(int nslot, int vgpr_per_slot) {
+// the occupancy the shape choice assumes is the one the kernel gets. A
+// prior matrix adds its column (one more value per slot).
+__host__ __device__ constexpr int grad_waves_per_simd(int nslot, int vgpr_per_slot,
+                                                      bool prior = false) {
     int need = vgpr_per_slot == 2 ? (29 * nslot + 80) / 2 : 7 * nslot + 28;
+    if (prior) need += nslot * vgpr_per_slot;
     need = (need + 7) / 8 * 8;
     int per_simd = 512 / need;  // 0: one wave does not fit, no narrow kernel
     return per_simd > 8 ? 8 : per_simd;
 }
-__host__ __device__ constexpr int grad_max_waves(int nslot, int vgpr_per_slot) {
-    int w = 4 * grad_waves_per_simd(nslot, vgpr_per_slot);
+__host__ __device__ constexpr int grad_max_waves(int nslot, int vgpr_per_slot, bool prior = false) {
+    int w = 4 * grad_waves_per_simd(nslot, vgpr_per_slot, prior);
     return w > kMaxWaves ? kMaxWaves : w;
 }
 
@@ -258,6 +261,7 @@ struct GradArgs {
     const void *emis;
     const double *em64;
     const double *lu_prefix;
+    const double *prior;  // prior copying matrix ([N][N], row i = column i), or null
     char *ws;
     GradLayout lay;
 };

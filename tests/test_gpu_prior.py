@@ -154,12 +154,12 @@ def test_prior_with_vector_mu_matches_oracle(ls, N, L, prec):
         _check(prec, _np(r["bck"].log_scale), ref["logG"][0], "log")
 
 
-def test_prior_unsupported_and_invalid(ls):
+def test_prior_invalid(ls):
     N, L = 70, 10
     H, rho, mu, Pi = _case(N, L, seed=4)
     m = ls.Model(H, N, rho, mu, prior=Pi)
     with pytest.raises(ls.LsError) as e:
-        ls.loglik_grad(m, prec="fp64", grad=True)
+        ls.loglik_grad(m, prec="f16", grad=True)  # as without a prior
     assert e.value.code == 4  # LS_ERR_UNSUPPORTED
     with pytest.raises(ValueError):
         ls.Model(H, N, rho, mu, prior=Pi[:-1])
@@ -209,3 +209,60 @@ def test_prior_forced_shapes(ls, prec, N, ns, nw):
     _check(prec, _np(r["bck"].log_scale), ref["logG"][0], "log")
     if prec == "fp64":
         rel_close(_np(r["bsnap"]), ref["B"], F64_RTOL, F64_ATOL_PROB)
+
+
+# ---------------------------------------------------------------------------
+# gradient under a prior matrix
+
+def _check_grad(ls, H, N, L, rho, mu, Pi, rec, prec):
+    ref = oracle.run_gradient(H, N, L, rho, mu, rec, prior=Pi)
+    m = ls.Model(H, N, rho, mu, prior=Pi)
+    out = ls.loglik_grad(m, rec, prec, grad=True)
+    plain = ls.loglik_grad(m, rec, prec, grad=False)
+    # log P is the same bits with and without the gradient
+    assert np.array_equal(out["loglik"].cpu().numpy(), plain["loglik"].cpu().numpy())
+    ll = ref["loglik"].sum()
+    assert abs(float(out["pac"].item()) - ll) <= (1e-12 if prec == "fp64" else F32_LOGLIK_RTOL) * abs(ll)
+    tol = 1e-10 if prec == "fp64" else 1e-6
+    if L > 1:
+        g = out["grad_rho"].cpu().numpy()
+        scale = max(np.abs(ref["grad_rho"]).sum(axis=0).max(), 1.0)
+        assert np.abs(g - ref["grad_rho"].sum(axis=0)).max() <= tol * scale
+    if np.ndim(mu) == 0:
+        scale = max(np.abs(ref["grad_mu"]).sum(), 1.0)
+        assert abs(float(out["grad_mu"].item()) - ref["grad_mu"].sum()) <= tol * scale
+    else:
+        gml = ref["grad_mu_l"]
+        M = (gml + 1.0 / (1.0 - mu)) / (1.0 / mu + 1.0 / (1.0 - mu))
+        parts = (M / mu + (1.0 - M) / (1.0 - mu)).sum(axis=0)
+        err = np.abs(out["grad_mu"].cpu().numpy() - gml.sum(axis=0)) / parts
+        assert err.max() <= (1e-12 if prec == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("N,L", [(2, 50), (40, 300), (130, 200), (40, 1), (40, 7), (40, 10)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_prior_gradient_vs_oracle(ls, N, L, prec):
+    """d PAC / d rho and d PAC / d mu under a skewed prior, all recipients;
+    L = 1, 7 and 10 give one-variant and short segments."""
+    H, rho, mu, Pi = _case(N, L, seed=5 * N + L)
+    _check_grad(ls, H, N, L, rho, mu, Pi, np.arange(N, dtype=np.int32), prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_prior_gradient_with_vector_mu(ls, prec):
+    N, L = 90, 120
+    H, rho, _, Pi = _case(N, L, seed=12)
+    mu = 10.0 ** np.random.default_rng(12).uniform(-4, -1, L)
+    _check_grad(ls, H, N, L, rho, mu, Pi, np.arange(N, dtype=np.int32), prec)
+
+
+@pytest.mark.parametrize("prec,N,ns,nw", [("fp32", 10000, 16, 13), ("fp64", 4000, 8, 13)])
+def test_prior_gradient_wide_groups(ls, prec, N, ns, nw):
+    """Groups wider than the prefetching adjoint kernel allows (its wide
+    variant, with the prior column), forced on a few recipients."""
+    from _gpu import forced_shape
+    L = 31
+    H, rho, mu, Pi = _case(N, L, seed=N + 9)
+    rec = np.array([0, 63, N // 2, N - 1], np.int32)
+    with forced_shape(ns, nw):
+        _check_grad(ls, H, N, L, rho, mu, Pi, rec, prec)
