@@ -26,10 +26,10 @@
                          and log-likelihoods vs the oracle on seeded
                          recipients
     python study.py c4var  the gradient workload (N = 2,000, L = 50,000) with a
-                         scalar and with a per-variant mu (log-uniform within
-                         a decade of the workload's mu): time per gradient in
-                         FP32 and FP64, and the gradient vs the oracle score
-                         on seeded recipients
+                         scalar mu, a per-variant mu (log-uniform within a
+                         decade of the workload's mu) and a skewed prior
+                         matrix: time per gradient in FP32 and FP64, and the
+                         gradient vs the oracle score on seeded recipients
     python study.py emu  (CPU only) numpy emulation of the FP32 forward sweep
                          against the same recursion in FP64, with the column
                          sum taken in the kernel's order, with Kahan lane sums
@@ -575,14 +575,19 @@ def study_c4var(args):
 
     x = make_inputs("c4")
     N, L = x["N"], x["L"]
-    mu_vec = x["mu"] * 10.0 ** np.random.default_rng(4).uniform(-1.0, 1.0, L)
+    rng = np.random.default_rng(4)
+    mu_vec = x["mu"] * 10.0 ** rng.uniform(-1.0, 1.0, L)
+    W = rng.random((N, N)) ** 3
+    np.fill_diagonal(W, 0.0)
+    Pi = W / W.sum(axis=0, keepdims=True)
     rec = seeded_recipients(N, args.recipients, seed=44)
-    out = {"study": "c4 gradient with a per-variant mu", "N": N, "L": L,
+    out = {"study": "c4 gradient with a per-variant mu and with a prior matrix", "N": N, "L": L,
            "oracle_recipients": len(rec)}
-    for name, mu in (("scalar_mu", x["mu"]), ("vector_mu", mu_vec)):
-        model = ls.Model(x["H"], N, x["rho"], mu)
+    for name, mu, prior in (("scalar_mu", x["mu"], None), ("vector_mu", mu_vec, None),
+                            ("prior_matrix", x["mu"], Pi)):
+        model = ls.Model(x["H"], N, x["rho"], mu, prior=prior)
         t0 = time.perf_counter()
-        ref = oracle.run_gradient(x["H"], N, L, x["rho"], mu, rec)
+        ref = oracle.run_gradient(x["H"], N, L, x["rho"], mu, rec, prior=prior)
         res = {"oracle_seconds": time.perf_counter() - t0}
         for prec in ("fp32", "fp64"):
             ls.loglik_grad(model, None, prec, grad=True)  # warm-up
@@ -609,6 +614,9 @@ def study_c4var(args):
                                         / out["scalar_mu"]["fp32"]["ms_per_gradient"])
     out["vector_mu_time_ratio_fp64"] = (out["vector_mu"]["fp64"]["ms_per_gradient"]
                                         / out["scalar_mu"]["fp64"]["ms_per_gradient"])
+    for prec in ("fp32", "fp64"):
+        out[f"prior_time_ratio_{prec}"] = (out["prior_matrix"][prec]["ms_per_gradient"]
+                                           / out["scalar_mu"][prec]["ms_per_gradient"])
     print(json.dumps(out), flush=True)
 
 
