@@ -396,8 +396,9 @@ hipError_t launch_symmetrise(const void *E, void *D, int32_t N, int32_t T, int i
 // ---------------------------------------------------------------------------
 // Emission tables of a per-variant mu, from (1-H)(1-2mu)+mu (appendix A.3) in
 // FP64: the FP64 pair as is; the FP32 pair divided by its larger member and
-// rounded once, with the log of that divisor; then the prefix sums of those
-// logs in index order (one thread, so the sums are fixed).
+// rounded once, with the log of that divisor (all threads, into
+// lu_prefix[l+1]); then the prefix sums of those logs in index order (one
+// thread, so the sums are fixed).
 __global__ void __launch_bounds__(256)
 emission_tables_kernel(const double *__restrict__ mu_vec, int32_t L, double *__restrict__ em64,
                        float *__restrict__ em32, double *__restrict__ lu_prefix) {
@@ -409,14 +410,14 @@ emission_tables_kernel(const double *__restrict__ mu_vec, int32_t L, double *__r
         const double unit = omu >= mu ? omu : mu;
         em32[2 * l] = (float)(omu / unit);
         em32[2 * l + 1] = (float)(mu / unit);
+        lu_prefix[l + 1] = log(unit);
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
         double acc = 0.0;
         lu_prefix[0] = 0.0;
         for (int l = 0; l < L; ++l) {
-            const double mu = mu_vec[l];
-            const double omu = (1.0 - 2.0 * mu) + mu;
-            acc += log(omu >= mu ? omu : mu);
+            acc += lu_prefix[l + 1];
             lu_prefix[l + 1] = acc;
         }
     }
