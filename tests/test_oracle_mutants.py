@@ -50,6 +50,16 @@ RHO_MAP_MUTANTS = {
     "rho_map_grad_drops_log": ("s * mg * log(m) * e", "s * mg * e"),
     "rho_map_grad_s_sign": ("gs += grad_rho[l] * mg * e;", "gs -= grad_rho[l] * mg * e;"),
 }
+# mistakes in the per-variant mu and prior-matrix paths, caught by the
+# enumeration pins under a random rational prior and a per-variant mu
+VARIANT_MUTANTS = {
+    "prior_transposed": ("return m->Pi ? m->Pi[(int64_t)i * m->N + j]",
+                         "return m->Pi ? m->Pi[(int64_t)j * m->N + i]"),
+    "mu_of_previous_variant": ("    double mu = mu_at(m, l);", "    double mu = mu_at(m, l > 0 ? l - 1 : 0);"),
+    "grad_mu_l_cumulative": ("            grad_mu_l[l] = gl;", "            grad_mu_l[l] = gmu;"),
+    "backward_norm_uniform_prior": ("g += prior(m, j, i) * theta(m, l, j, i) * beta[j];",
+                                    "g += (j == i ? 0.0 : theta(m, l, j, i) * beta[j] / (double)(m->N - 1));"),
+}
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_printed_values.json")
 
 
@@ -103,11 +113,55 @@ def _pins_pass(lib) -> bool:
     return True
 
 
+def _variant_pins_pass(lib) -> bool:
+    """Enumeration pins with a random rational prior matrix and a mutation
+    probability per variant: posteriors, both likelihoods, d/d rho and
+    d/d mu^l."""
+    L, N = 5, 4
+    h01 = (np.random.default_rng(21).random((L, N)) < 0.5).astype(np.uint8)
+    W = np.random.default_rng(21).integers(1, 10, size=(N, N))
+    Pi = [[Fraction(0)] * N for _ in range(N)]
+    for i in range(N):
+        tot = sum(int(W[j, i]) for j in range(N) if j != i)
+        for j in range(N):
+            if j != i:
+                Pi[j][i] = Fraction(int(W[j, i]), tot)
+    Pf = np.array([[float(x) for x in row] for row in Pi])
+    rho = [Fraction(k, 32) for k in (3, 17, 1, 29)]
+    mu = [Fraction(k, 32) for k in (1, 3, 2, 8, 1)]
+    rf, mf = np.array([float(r) for r in rho]), np.array([float(m) for m in mu])
+    H, rec, tg = pack_haplotypes(h01), np.arange(N, dtype=np.int32), np.arange(L, dtype=np.int32)
+    res = oracle.run_pass(H, N, L, rf, mf, rec, tg, want=("P",), nthreads=1, lib=lib, prior=Pf)
+    gr = oracle.run_gradient(H, N, L, rf, mf, rec, nthreads=1, lib=lib, prior=Pf)
+    for i in range(N):
+        ex = enumerate_exact(h01.tolist(), rho, mu, i, prior=Pi)
+        logP = np.log(float(ex["P"]))
+        post = np.array([[float(x) for x in row] for row in ex["post"]])
+        ok = (abs(res["llf"][i] - logP) <= 1e-12 * abs(logP)
+              and abs(res["llb"][i] - logP) <= 1e-12 * abs(logP)
+              and np.allclose(res["P"][:, i, :], post, rtol=1e-11, atol=1e-15)
+              and np.allclose(gr["grad_rho"][i], [float(x) for x in ex["dlogP_drho"]],
+                              rtol=1e-9, atol=1e-12)
+              and np.allclose(gr["grad_mu_l"][i], [float(x) for x in ex["dlogP_dmu_l"]],
+                              rtol=1e-9, atol=1e-9))
+        if not ok:
+            return False
+    return True
+
+
+@pytest.mark.parametrize("name", sorted(VARIANT_MUTANTS))
+def test_variant_pins_catch_mutant(tmp_path, name):
+    find, repl = VARIANT_MUTANTS[name]
+    lib = _build_mutant(tmp_path, name, find, repl)
+    assert not _variant_pins_pass(lib), f"pins did not catch mutant {name}"
+
+
 def test_unmutated_copy_passes(tmp_path):
     lib = _build_mutant(tmp_path, "identity", "LSO_EPS 2.220446049250313080847e-16",
                         "LSO_EPS 2.220446049250313080847e-16")
     assert _pins_pass(lib)
     assert _rho_map_pins_pass(lib)
+    assert _variant_pins_pass(lib)
 
 
 @pytest.mark.parametrize("name", sorted(RHO_MAP_MUTANTS))
