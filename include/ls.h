@@ -112,8 +112,14 @@ typedef struct {
                              uniform prior 1/(N-1). Used by decoding, the
                              log-likelihood and its gradient, with a scalar
                              mu or mu_vec, in every precision that offers
-                             them. The caller keeps it alive and unchanged
-                             while the model is in use. */
+                             them. With LS_FP32_F16STORE a backward table
+                             entry is 16384 v_j / sum_k (N-1) Pi_ki v_k,
+                             which can exceed the half range when the
+                             prior gives the copied donors far less than
+                             average weight; the status then reports
+                             LS_FLAG_NONFINITE (use LS_FP32). The caller
+                             keeps it alive and unchanged while the model
+                             is in use. */
 } ls_model;
 
 /* Device bytes of the workspace ls_model_init lays the internal haplotype
