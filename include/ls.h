@@ -116,8 +116,9 @@ typedef struct {
                              entry is 16384 v_j / sum_k (N-1) Pi_ki v_k,
                              which can exceed the half range when the
                              prior gives the copied donors far less than
-                             average weight; the status then reports
-                             LS_FLAG_NONFINITE (use LS_FP32). The caller
+                             average weight; a sweep that resumes from such
+                             a table reports LS_FLAG_NONFINITE (use
+                             LS_FP32). The caller
                              keeps it alive and unchanged while the model
                              is in use. */
 } ls_model;
