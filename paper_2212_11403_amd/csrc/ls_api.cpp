@@ -704,7 +704,7 @@ const char *ls_status_string(ls_status s) {
     case LS_ERR_ARG: return "invalid argument";
     case LS_ERR_SHAPE: return "inconsistent sizes";
     case LS_ERR_STATE: return "table in the wrong state for this call";
-    case LS_ERR_UNSUPPORTED: return "N too large for this precision on one GPU";
+    case LS_ERR_UNSUPPORTED: return "N too large for this precision on one GPU, or not offered in it";
     case LS_ERR_DEVICE: return "HIP runtime error";
     case LS_ERR_WORKSPACE: return "workspace missing or too small";
     case LS_WARN_NONFINITE: return "a column sum was zero or non-finite";

@@ -49,12 +49,15 @@ def test_struct_layouts_match_header():
     from paper_2212_11403_amd._lib import LsModel, LsTable
     assert ctypes.sizeof(LsModel) == 88
     assert ctypes.sizeof(LsTable) == 56
+    # the optional fields follow the ones ls_model_init sets, in header order
+    assert LsModel.mu_vec.offset == 72 and LsModel.prior.offset == 80
 
 
 def test_host_only_calls(lib):
     assert lib.ls_version().decode().startswith("libls")
     assert lib.ls_status_string(0).decode() == "ok"
     assert lib.ls_status_string(16).decode().startswith("a column sum")
+    assert lib.ls_status_string(4).decode().startswith("N too large")
     assert lib.ls_model_workspace_bytes(1, 10) == 0
     # internal rows: two copies of floor(N/64) words plus the partial word,
     # padded to 64 B, the whole rounded up to 256 B; then four tables of L
