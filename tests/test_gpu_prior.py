@@ -266,3 +266,26 @@ def test_prior_gradient_wide_groups(ls, prec, N, ns, nw):
     rec = np.array([0, 63, N // 2, N - 1], np.int32)
     with forced_shape(ns, nw):
         _check_grad(ls, H, N, L, rho, mu, Pi, rec, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_prior_large_n(ls, prec):
+    """N = 16,384 (a 2 GiB prior): the widest groups the prior column leaves
+    room for, on a few recipients against the oracle."""
+    N, L = 16384, 8
+    rng = np.random.default_rng(16384)
+    h = (rng.random((L, N)) < 0.3).astype(np.uint8)
+    rho = rho_from_spacings(rng.exponential(0.05, L - 1))
+    Pi = rng.random((N, N))
+    Pi **= 3
+    np.fill_diagonal(Pi, 0.0)
+    Pi /= Pi.sum(axis=0, keepdims=True)
+    H = pack_haplotypes(h)
+    rec = np.array([0, 4095, 8192, N - 1], np.int32)
+    targets = np.array([0, 5], np.int32)
+    ref = oracle.run_pass(H, N, L, rho, 0.01, rec, targets, want=("P", "logG"), prior=Pi)
+    m = ls.Model(H, N, rho, 0.01, prior=Pi)
+    r = ls.decode(m, targets, prec, recipients=rec, want=("P",))
+    _check(prec, _np(r["P"]), ref["P"], "prob")
+    _check(prec, _np(r["fwd"].log_scale), ref["llf"], "log")
+    _check(prec, _np(r["bck"].log_scale), ref["logG"][0], "log")
