@@ -77,6 +77,9 @@ def enumerate_exact(h, rho, mu, i, prior=None):
             for t in tr:
                 rest *= t
             dP_dmu[l] += rest * d
+    if P == 0:
+        # every path has probability 0: the posterior is undefined
+        return dict(P=P, post=None)
     post = [[marg[l][j] / P for j in range(N)] for l in range(L)]
     return dict(P=P, post=post, dlogP_drho=[d / P for d in dP_drho],
                 dlogP_dmu=sum(dP_dmu) / P, dlogP_dmu_l=[d / P for d in dP_dmu])
@@ -210,4 +213,100 @@ def rho_map_checks(calc_rho, rho_map_grad, printed_pairs) -> bool:
     fdg = (f(s, ga + hg) - f(s, ga - hg)) / (2 * hg)
     ok &= abs(gs - fds) <= 1e-7 * abs(fds)
     ok &= abs(gg - fdg) <= 1e-7 * abs(fdg)
+    return bool(ok)
+
+
+# ---------------------------------------------------------------------------
+# The floor and the zero-total rule of the posterior (section 2.2, eq.
+# postprob) and of the distance (section 2.1, eq. distmat). The constant is
+# double precision machine epsilon, taken from numpy's description of the
+# type (the paper prints it as about 2.22e-16), not from the code under test.
+
+EPS64 = float(np.finfo(np.float64).eps)
+
+
+def zero_sum_case():
+    """A recipient whose forward and backward vectors at target t are finite
+    and non-zero but have disjoint support, so sum_j alpha_j beta_j = 0.
+
+    mu = 0 (an emission is 0 on every mismatch) and rho_t = 0 (no switch
+    between t and t+1). Recipient 0 carries allele 1 at t and at t+1; donors
+    1 and 2 match it at t and not at t+1, donor 3 the reverse; at every other
+    variant all four haplotypes carry allele 0. alpha^t lives on donors 1 and
+    2 only (donor 3 mismatches at t) and beta^t on donor 3 only (with
+    rho_t = 0, beta^t_j is proportional to theta^{t+1}_j beta^{t+1}_j), so
+    every copying path has probability 0.
+
+    Returns (h01 [L][N], rho as Fractions [L-1], mu, recipient, target)."""
+    L, N, t = 5, 4, 2
+    h = np.zeros((L, N), dtype=np.uint8)
+    h[t, [0, 1, 2]] = 1
+    h[t + 1, [0, 3]] = 1
+    rho = [Fraction(1, 4), Fraction(1, 2), Fraction(0), Fraction(1, 8)]
+    return h, rho, Fraction(0), 0, t
+
+
+def tiny_posterior_case():
+    """Exact posteriors spanning many orders of magnitude: mu = 2^-40, so
+    that a donor mismatching the recipient where it is copied has a
+    posterior near mu times the switch probabilities around it. Some exact
+    posteriors fall below 2^-52 and many between 2^-52 and single
+    precision's epsilon 2^-23. Returns (h01, rho Fractions, mu Fraction)."""
+    h = np.array([[0, 1, 0, 0],
+                  [0, 0, 0, 0],
+                  [1, 0, 0, 1],
+                  [0, 0, 1, 0],
+                  [1, 0, 0, 1],
+                  [1, 0, 0, 1]], dtype=np.uint8)
+    rho = [Fraction(k, 256) for k in (17, 27, 37, 2, 3)]
+    return h, rho, Fraction(1, 2 ** 40)
+
+
+def floor_checks(run_pass) -> bool:
+    """The zero-total rule and the eps floor, against exact enumeration.
+
+    ``run_pass(h01, rho_float, mu_float, recipients, targets)`` returns the
+    oracle's dict with P and E. Checks: (1) in zero_sum_case the exact
+    likelihood is 0 (so eq. postprob has no value) and the pass gives
+    p_ji = eps for every donor, p_ii = 0, and half distances -log(eps)/2 =
+    26 log 2; (2) in tiny_posterior_case the half distances equal
+    -log(max(p, eps))/2 of the exact posteriors, with entries on both sides
+    of the floor and some between eps and single precision's epsilon."""
+    ok = True
+    h, rho, mu, i, t = zero_sum_case()
+    ex = enumerate_exact(h.tolist(), rho, mu, i)
+    ok &= ex["P"] == 0 and ex["post"] is None
+    res = run_pass(h, np.array([float(r) for r in rho]), float(mu), np.array([i], np.int32),
+                   np.array([t], np.int32))
+    P, E = res["P"][0, 0], res["E"][0, 0]
+    donors = np.arange(h.shape[1]) != i
+    ok &= bool(np.all(P[donors] == EPS64)) and P[i] == 0.0
+    half = 26.0 * np.log(2.0)  # -log(2^-52) / 2
+    ok &= bool(np.all(np.abs(E[donors] - half) <= 1e-14 * half)) and E[i] == 0.0
+
+    h, rho, mu = tiny_posterior_case()
+    L, N = h.shape
+    rec = np.arange(N, dtype=np.int32)
+    tg = np.arange(L, dtype=np.int32)
+    res = run_pass(h, np.array([float(r) for r in rho]), float(mu), rec, tg)
+    below = between = 0
+    for i in range(N):
+        ex = enumerate_exact(h.tolist(), rho, mu, i)
+        post = np.array([[float(x) for x in row] for row in ex["post"]])
+        # the floor decides on the exact posterior; entries within one
+        # rounding of eps would be ambiguous, and none is that close here
+        Eref = np.empty((L, N))
+        for l in range(L):
+            for j in range(N):
+                if j == i:
+                    Eref[l, j] = 0.0
+                    continue
+                q = ex["post"][l][j]
+                ok &= abs(float(q) / EPS64 - 1.0) > 1e-6
+                Eref[l, j] = -np.log(float(q) if q > Fraction(EPS64) else EPS64) / 2
+                below += q < Fraction(EPS64)
+                between += Fraction(EPS64) < q < Fraction(2.0 ** -23)
+        ok &= bool(np.allclose(res["P"][:, i, :], post, rtol=1e-11, atol=1e-300))
+        ok &= bool(np.allclose(res["E"][:, i, :], Eref, rtol=1e-12, atol=1e-13))
+    ok &= below >= 4 and between >= 10
     return bool(ok)

@@ -18,7 +18,7 @@ import pytest
 import oracle
 from lsinputs import pack_haplotypes
 
-from _pins import enumerate_exact, rho_map_checks
+from _pins import enumerate_exact, floor_checks, rho_map_checks
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "ls_oracle.c")
 
@@ -60,6 +60,15 @@ VARIANT_MUTANTS = {
     "backward_norm_uniform_prior": ("g += prior(m, j, i) * theta(m, l, j, i) * beta[j];",
                                     "g += (j == i ? 0.0 : theta(m, l, j, i) * beta[j] / (double)(m->N - 1));"),
 }
+# mistakes in the eps floor and the zero-total rule of the posterior (eq.
+# postprob, eq. distmat), caught by the floor pins
+FLOOR_MUTANTS = {
+    "eps_single_precision": ("#define LSO_EPS 2.220446049250313080847e-16",
+                             "#define LSO_EPS 1.1920928955078125e-07"),
+    "zero_sum_branch_dropped": ("        else if (Z == 0.0)\n            p[j] = LSO_EPS;\n", ""),
+    "zero_sum_gives_zero": ("            p[j] = LSO_EPS;\n        else", "            p[j] = 0.0;\n        else"),
+    "floor_not_applied": ("double q = (p < LSO_EPS) ? LSO_EPS : p;", "double q = p;"),
+}
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_printed_values.json")
 
 
@@ -68,6 +77,14 @@ def _rho_map_pins_pass(lib) -> bool:
     pairs = json.load(open(GOLDEN))["calc_rho"]["pairs"]
     return rho_map_checks(lambda c, s, g: oracle.calc_rho(c, s, g, lib=lib),
                           lambda c, s, g, gr: oracle.rho_map_grad(c, s, g, gr, lib=lib), pairs)
+
+
+def _floor_pins_pass(lib) -> bool:
+    def run(h01, rho, mu, rec, tg):
+        L, N = h01.shape
+        return oracle.run_pass(pack_haplotypes(h01), N, L, rho, mu, rec, tg, want=("P", "E"),
+                               nthreads=1, lib=lib)
+    return floor_checks(run)
 
 
 def _build_mutant(tmp_path, name, find, repl):
@@ -162,6 +179,14 @@ def test_unmutated_copy_passes(tmp_path):
     assert _pins_pass(lib)
     assert _rho_map_pins_pass(lib)
     assert _variant_pins_pass(lib)
+    assert _floor_pins_pass(lib)
+
+
+@pytest.mark.parametrize("name", sorted(FLOOR_MUTANTS))
+def test_floor_pins_catch_mutant(tmp_path, name):
+    find, repl = FLOOR_MUTANTS[name]
+    lib = _build_mutant(tmp_path, name, find, repl)
+    assert not _floor_pins_pass(lib), f"pins did not catch mutant {name}"
 
 
 @pytest.mark.parametrize("name", sorted(RHO_MAP_MUTANTS))

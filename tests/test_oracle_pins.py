@@ -16,8 +16,9 @@ import oracle
 from lsinputs import (evenly_spaced_targets, make_inputs, pack_haplotypes, packed_bytes,
                       rho_from_spacings, unpack_haplotypes)
 
-from _pins import (enumerate_exact, logdomain_fb, raw_forward, rho0_closed_form,
-                   rho0_closed_form_grad, rho1_closed_form, rho_map_checks)
+from _pins import (EPS64, enumerate_exact, floor_checks, logdomain_fb, raw_forward,
+                   rho0_closed_form, rho0_closed_form_grad, rho1_closed_form, rho_map_checks,
+                   tiny_posterior_case, zero_sum_case)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_printed_values.json")
 
@@ -382,6 +383,37 @@ def test_oracle_recombination_map():
 def test_oracle_epsilon_matches_paper():
     g = json.load(open(GOLDEN))["epsilon"]
     assert abs(oracle.EPS - g["approx"]) < 5e-19
+    assert EPS64 == 2.0 ** -52 and abs(EPS64 - g["approx"]) < 5e-19
+
+
+def test_zero_total_posterior_rule():
+    """eq. postprob, section 2.2: where sum_j alpha_j beta_j = 0 every donor
+    gets p_ji = eps, and eq. distmat then gives -log(eps)/2 = 26 log 2. The
+    case is built so that alpha^t and beta^t are finite and non-zero with
+    disjoint supports (zero_sum_case); exact enumeration confirms that every
+    copying path has probability 0."""
+    h, rho, mu, i, t = zero_sum_case()
+    L, N = h.shape
+    ex = enumerate_exact(h.tolist(), rho, mu, i)
+    assert ex["P"] == 0
+    res = _run(h, [float(r) for r in rho], float(mu), np.array([i], np.int32),
+               np.array([t], np.int32), want=("A", "B", "P", "E"))
+    a, b = res["A"][0, 0], res["B"][0, 0]
+    assert np.all(np.isfinite(a)) and np.all(np.isfinite(b))
+    assert a.sum() > 0 and b.sum() > 0 and np.dot(a, b) == 0.0
+    donors = np.arange(N) != i
+    assert np.all(res["P"][0, 0, donors] == EPS64) and res["P"][0, 0, i] == 0.0
+    np.testing.assert_allclose(res["E"][0, 0, donors], 26.0 * np.log(2.0), rtol=1e-15)
+    assert res["E"][0, 0, i] == 0.0
+
+
+def test_epsilon_floor_on_tiny_posteriors():
+    """eq. distmat floors p at eps = 2^-52 before the log: against the exact
+    posteriors of a case with entries below 2^-52 and between 2^-52 and
+    2^-23, and with the zero-total case above (floor_checks)."""
+    def run(h01, rho, mu, rec, tg):
+        return _run(h01, rho, mu, rec, tg, want=("P", "E"))
+    assert floor_checks(run)
 
 
 def test_packing_round_trip_and_bit_order():
