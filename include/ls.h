@@ -16,9 +16,12 @@
  * - Indices are 0-based. Haplotypes 0..N-1, variants 0..L-1. rho[l] is the
  *   recombination probability between variants l and l+1, l = 0..L-2 (the
  *   paper's rho vector of length L-1, section 3.4).
- * - The copying prior is uniform: pi_ji = 1/(N-1) for j != i and 0 for
- *   j == i (the default prior of section 2.1; self copying excluded).
- * - The mutation probability mu is one scalar for all variants.
+ * - The copying prior is uniform, pi_ji = 1/(N-1) for j != i and 0 for
+ *   j == i (the default prior of section 2.1; self copying excluded),
+ *   unless the model carries a prior copying matrix (ls_model.prior).
+ * - The mutation probability is the scalar ls_model.mu at every variant,
+ *   unless the model carries one value per variant (ls_model.mu_vec,
+ *   section 3.4).
  * - Every data pointer named "device" is device memory on the current HIP
  *   device. Pointers named "host" are host memory. The caller allocates and
  *   owns every buffer; the library allocates nothing and keeps no global
@@ -183,13 +186,24 @@ ls_status ls_table_copy(ls_table *dst, const ls_table *src, int32_t N, void *str
  *   P[k][r][j] = p_{j,i}                         posterior (eq. postprob)
  *   E[k][r][j] = -log(max(p_{j,i}, eps)) / 2     half distance, eps = 2^-52
  *                                                (eq. distmat), E[k][r][i] = 0
- * bsnap, P, E: device, [T][R][N]; element type double for LS_FP64, float
+ * bsnap: device, [T][R][N]; element type double for LS_FP64, float
  * otherwise. bsnap[k] must be a backward table state at targets[k] for the
  * same recipients (as written by ls_backward's snapshots); it may be NULL
- * only if T == 0. Errors: LS_ERR_ARG, LS_ERR_STATE, LS_ERR_UNSUPPORTED,
+ * only if T == 0.
+ * P, E: device, same element type; row (k, r) starts at element
+ * k * out_target_stride + r * out_row_stride and holds N entries. Strides
+ * of 0 mean the contiguous [T][R][N] layout (out_row_stride = N,
+ * out_target_stride = R * out_row_stride). Other strides let a window of
+ * recipients write its rows into larger arrays, e.g. rows r0 .. r0+R-1 of
+ * T resident N x N matrices (pass E + r0 * N, out_target_stride = N * N,
+ * out_row_stride = N), the recipient windows of section 3.9. Rows must not
+ * overlap: out_row_stride >= N and, for T > 1, out_target_stride >=
+ * (R-1) * out_row_stride + N, else LS_ERR_SHAPE. P and E share the layout.
+ * Errors: LS_ERR_ARG, LS_ERR_SHAPE, LS_ERR_STATE, LS_ERR_UNSUPPORTED,
  * LS_ERR_DEVICE. */
 ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t *targets,
-                     int32_t T, const void *bsnap, void *P, void *E, void *stream);
+                     int32_t T, const void *bsnap, void *P, void *E, int64_t out_target_stride,
+                     int64_t out_row_stride, void *stream);
 
 /* Backward (cf. Backward(bck, pars, t), section 3.6): moves `bck` from its
  * current variant down to t (t < bck->l; an unpropagated table starts at
@@ -248,6 +262,26 @@ ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R
                          ls_precision prec, double *loglik, double *pac, double *grad_rho,
                          double *grad_mu, void *workspace, size_t ws_bytes, void *stream);
 
+/* The two halves of ls_loglik_grad with a gradient, for callers that
+ * evaluate the log-likelihood first and decide later whether they need its
+ * gradient (an autograd forward and backward):
+ * ls_loglik_checkpoint runs the checkpointing forward sweep and writes
+ * loglik (may be NULL) and pac, exactly as ls_loglik_grad does (the same
+ * bits); it leaves the forward checkpoints in `workspace`.
+ * ls_loglik_grad_adjoint then runs the recompute and adjoint passes over
+ * those checkpoints and writes grad_rho and grad_mu, the same bits as
+ * ls_loglik_grad. Both calls take the same model, recipients, R,
+ * precision and workspace (size from ls_loglik_grad_workspace_bytes); the
+ * workspace must not be changed between them (nothing checks this: device
+ * memory is not read back). LS_FP64 and LS_FP32 only (LS_ERR_UNSUPPORTED
+ * otherwise). Errors as ls_loglik_grad. */
+ls_status ls_loglik_checkpoint(const ls_model *m, const int32_t *recipients, int32_t R,
+                               ls_precision prec, double *loglik, double *pac, void *workspace,
+                               size_t ws_bytes, void *stream);
+ls_status ls_loglik_grad_adjoint(const ls_model *m, const int32_t *recipients, int32_t R,
+                                 ls_precision prec, double *grad_rho, double *grad_mu,
+                                 void *workspace, size_t ws_bytes, void *stream);
+
 /* Recombination probabilities from a genetic map (eq. rho, section 2.1;
  * the paper's CalcRho, section 3.4):
  *   rho[l] = 1 - exp(-s (cM[l] / 100)^gamma),  l = 0 .. n-1,
@@ -279,11 +313,14 @@ size_t ls_loglik_grad_workspace_bytes(const ls_model *m, int32_t R, ls_precision
  * any has LS_FLAG_BAD_RECIPIENT. */
 ls_status ls_status_check(const uint32_t *status, int32_t R, void *stream);
 
-/* The kernel shape the library would use for N haplotypes at `prec`:
- * slots (64-donor register groups) per wave and waves per recipient.
- * Returns LS_ERR_UNSUPPORTED if no shape fits on one compute unit. */
-ls_status ls_kernel_shape(int32_t N, ls_precision prec, int32_t *slots_per_wave,
-                          int32_t *waves_per_recipient);
+/* The kernel shape the library uses for the sweeps of N haplotypes at
+ * `prec`: slots (64-donor register groups) per wave and waves per
+ * recipient. with_prior != 0: the shape of a model with a prior matrix
+ * (whose sweeps keep the prior column in registers beside the donor
+ * column). Returns LS_ERR_UNSUPPORTED if no shape fits on one compute unit,
+ * LS_ERR_ARG for N < 2 or an unknown precision. */
+ls_status ls_kernel_shape(int32_t N, ls_precision prec, int32_t with_prior,
+                          int32_t *slots_per_wave, int32_t *waves_per_recipient);
 
 const char *ls_status_string(ls_status s);
 const char *ls_version(void);

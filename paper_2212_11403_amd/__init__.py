@@ -14,7 +14,7 @@ __all__ = [
     "LS_FP32", "LS_FP32_F16STORE", "LS_FP64", "LS_MAX_TARGETS", "LS_OK", "LS_WARN_NONFINITE",
     "LsError", "load", "Model", "Table", "forward", "backward", "posterior_distance",
     "distance_symmetrise", "loglik_grad", "kernel_shape", "status_check", "decode",
-    "PACLoglik", "RhoMap", "calc_rho", "rho_map_grad",
+    "PACLoglik", "RhoMap", "calc_rho", "rho_map_grad", "distance_matrices",
 ]
 
 
@@ -23,7 +23,7 @@ def __getattr__(name):
     # package (e.g. to build it) does not pull in torch
     if name in ("Model", "Table", "forward", "backward", "posterior_distance",
                 "distance_symmetrise", "loglik_grad", "kernel_shape", "status_check", "decode",
-                "io_dtype", "prec_code", "calc_rho", "rho_map_grad"):
+                "io_dtype", "prec_code", "calc_rho", "rho_map_grad", "distance_matrices"):
         from . import api
         return getattr(api, name)
     if name in ("PACLoglik", "RhoMap"):

@@ -31,6 +31,7 @@ EXPORTED = [
     "ls_forward", "ls_backward", "ls_posterior_distance", "ls_distance_symmetrise",
     "ls_loglik_grad", "ls_loglik_grad_workspace_bytes", "ls_status_check",
     "ls_kernel_shape", "ls_status_string", "ls_version", "ls_calc_rho", "ls_rho_map_grad",
+    "ls_loglik_checkpoint", "ls_loglik_grad_adjoint",
 ]
 
 
@@ -103,14 +104,16 @@ def load():
         "ls_model_init": (ctypes.c_int, [M, P, SZ, P]),
         "ls_table_init": (ctypes.c_int, [T, I32, ctypes.c_int, P, P, P, P, I32, P]),
         "ls_table_copy": (ctypes.c_int, [T, T, I32, P]),
-        "ls_forward": (ctypes.c_int, [T, M, I32, P, I32, P, P, P, P]),
+        "ls_forward": (ctypes.c_int, [T, M, I32, P, I32, P, P, P, I64, I64, P]),
         "ls_backward": (ctypes.c_int, [T, M, I32, P, I32, P, P]),
         "ls_posterior_distance": (ctypes.c_int, [T, T, M, P, P, P]),
         "ls_distance_symmetrise": (ctypes.c_int, [P, P, I32, I32, ctypes.c_int, P]),
         "ls_loglik_grad": (ctypes.c_int, [M, P, I32, ctypes.c_int, P, P, P, P, P, SZ, P]),
         "ls_loglik_grad_workspace_bytes": (SZ, [M, I32, ctypes.c_int]),
+        "ls_loglik_checkpoint": (ctypes.c_int, [M, P, I32, ctypes.c_int, P, P, P, SZ, P]),
+        "ls_loglik_grad_adjoint": (ctypes.c_int, [M, P, I32, ctypes.c_int, P, P, P, SZ, P]),
         "ls_status_check": (ctypes.c_int, [P, I32, P]),
-        "ls_kernel_shape": (ctypes.c_int, [I32, ctypes.c_int, ctypes.POINTER(I32),
+        "ls_kernel_shape": (ctypes.c_int, [I32, ctypes.c_int, I32, ctypes.POINTER(I32),
                                            ctypes.POINTER(I32)]),
         "ls_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "ls_version": (ctypes.c_char_p, []),

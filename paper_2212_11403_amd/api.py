@@ -71,29 +71,14 @@ class Model:
         self.H = H.to(dev).contiguous()
         if self.H.dtype not in (torch.int32, torch.uint32):
             raise ValueError("H must hold 32-bit words")
+        self.device = dev
         L = int(self.H.shape[0])
-        rho = torch.as_tensor(np.asarray(rho, dtype=np.float64) if not torch.is_tensor(rho)
-                              else rho, dtype=torch.float64)
-        self.rho = rho.to(dev).contiguous()
-        if self.rho.numel() != max(L - 1, 0):
-            raise ValueError("rho must have L-1 entries")
         self.c = LsModel()
         self.c.H = self.H.data_ptr()
         self.c.stride_words = int(self.H.shape[1])
         self.c.N = int(N)
         self.c.L = L
-        self.c.rho = self.rho.data_ptr() if self.rho.numel() else None
-        self.mu_vec = None
-        if np.ndim(mu) == 0 and not (torch.is_tensor(mu) and mu.dim() > 0):
-            self.c.mu = float(mu)
-        else:
-            muv = mu.to(torch.float64) if torch.is_tensor(mu) else \
-                torch.as_tensor(np.asarray(mu, dtype=np.float64))
-            self.mu_vec = muv.to(dev).contiguous().reshape(-1)
-            if self.mu_vec.numel() != L:
-                raise ValueError("a per-variant mu must have L entries")
-            self.c.mu = 0.0
-            self.c.mu_vec = self.mu_vec.data_ptr()
+        self._set_params(rho, mu)
         self.prior = None
         if prior is not None:
             Pi = prior.to(torch.float64) if torch.is_tensor(prior) else \
@@ -109,7 +94,36 @@ class Model:
         self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
         check(lib.ls_model_init(ctypes.byref(self.c), _p(self.workspace), nbytes,
                                 _stream(stream)), "ls_model_init")
-        self.device = dev
+
+    def _set_params(self, rho, mu):
+        L = self.c.L
+        rho = torch.as_tensor(np.asarray(rho, dtype=np.float64) if not torch.is_tensor(rho)
+                              else rho, dtype=torch.float64)
+        self.rho = rho.to(self.device).contiguous()
+        if self.rho.numel() != max(L - 1, 0):
+            raise ValueError("rho must have L-1 entries")
+        self.c.rho = self.rho.data_ptr() if self.rho.numel() else None
+        self.mu_vec = None
+        self.c.mu_vec = None
+        if np.ndim(mu) == 0 and not (torch.is_tensor(mu) and mu.dim() > 0):
+            self.c.mu = float(mu)
+        else:
+            muv = mu.to(torch.float64) if torch.is_tensor(mu) else \
+                torch.as_tensor(np.asarray(mu, dtype=np.float64))
+            self.mu_vec = muv.to(self.device).contiguous().reshape(-1)
+            if self.mu_vec.numel() != L:
+                raise ValueError("a per-variant mu must have L entries")
+            self.c.mu = 0.0
+            self.c.mu_vec = self.mu_vec.data_ptr()
+
+    def update(self, rho, mu, stream=None):
+        """New rho and mu for the same haplotypes (and prior): re-runs
+        ls_model_init in the existing workspace. Tables made under the old
+        parameters are refused afterwards (their model hash differs)."""
+        self._set_params(rho, mu)
+        lib = _lib.load()
+        check(lib.ls_model_init(ctypes.byref(self.c), _p(self.workspace),
+                                int(self.workspace.numel()), _stream(stream)), "ls_model_init")
 
     @property
     def N(self) -> int:
@@ -155,6 +169,19 @@ class Table:
     def R(self) -> int:
         return self.c.R
 
+    def reset(self, model: Model, recipients, stream=None):
+        """Re-initialise this table's buffers for other recipients (at most
+        as many as it was made for): "not yet propagated" (ResetTable)."""
+        rec = recipients.to(model.device, torch.int32).contiguous() if torch.is_tensor(recipients) \
+            else torch.as_tensor(np.asarray(recipients, dtype=np.int32)).to(model.device)
+        R = int(rec.numel())
+        if R < 1 or R > self.state.shape[0]:
+            raise ValueError("reset: recipient count must be in [1, capacity]")
+        self.recipients = rec
+        check(_lib.load().ls_table_init(ctypes.byref(self.c), int(self.c.direction), self.prec,
+                                        _p(self.state), _p(self.log_scale), _p(self.status),
+                                        _p(rec), R, _stream(stream)), "ls_table_init")
+
     def copy_from(self, src: "Table", stream=None):
         """CopyTable(self, src)."""
         check(_lib.load().ls_table_copy(ctypes.byref(self.c), ctypes.byref(src.c), self.N,
@@ -163,11 +190,16 @@ class Table:
 
 
 def forward(table: Table, model: Model, t: int, targets=None, bsnap=None, P=None, E=None,
-            stream=None):
+            stream=None, out_strides=(0, 0)):
+    """Forward(table, model, t); at the targets, posteriors P and half
+    distances E from the snapshots bsnap ([T][R][N]). out_strides = (target
+    stride, row stride) of P and E in elements; (0, 0): contiguous
+    [T][R][N]."""
     T = 0 if targets is None else len(targets)
     check(_lib.load().ls_forward(ctypes.byref(table.c), ctypes.byref(model.c), int(t),
                                  _i32_host(targets), T, _p(bsnap), _p(P), _p(E),
-                                 _stream(stream)), "ls_forward")
+                                 int(out_strides[0]), int(out_strides[1]), _stream(stream)),
+          "ls_forward")
 
 
 def backward(table: Table, model: Model, t: int, targets=None, bsnap=None, stream=None):
@@ -203,10 +235,12 @@ def status_check(table: Table, stream=None) -> int:
     return code
 
 
-def kernel_shape(N: int, prec="fp32"):
+def kernel_shape(N: int, prec="fp32", prior: bool = False):
+    """(slots per wave, waves per recipient) of the sweeps for N haplotypes;
+    prior=True: for a model with a prior copying matrix."""
     a, b = ctypes.c_int32(0), ctypes.c_int32(0)
-    check(_lib.load().ls_kernel_shape(int(N), prec_code(prec), ctypes.byref(a), ctypes.byref(b)),
-          "ls_kernel_shape")
+    check(_lib.load().ls_kernel_shape(int(N), prec_code(prec), int(bool(prior)), ctypes.byref(a),
+                                      ctypes.byref(b)), "ls_kernel_shape")
     return a.value, b.value
 
 
@@ -266,6 +300,46 @@ def loglik_grad(model: Model, recipients=None, prec="fp32", grad: bool = True, s
     return out
 
 
+class Checkpoints:
+    """Forward checkpoints of a log-likelihood evaluation kept for a later
+    gradient (ls_loglik_checkpoint / ls_loglik_grad_adjoint). Holds the
+    workspace; the model must not change in between."""
+
+    def __init__(self, model: Model, recipients=None, prec="fp32", stream=None):
+        lib = _lib.load()
+        self.model = model
+        self.prec = prec_code(prec)
+        dev = model.device
+        self.rec = None
+        if recipients is not None:
+            self.rec = torch.as_tensor(np.asarray(recipients, dtype=np.int32)).to(dev) \
+                if not torch.is_tensor(recipients) else recipients.to(dev, torch.int32).contiguous()
+        self.R = model.N if self.rec is None else int(self.rec.numel())
+        self.nbytes = lib.ls_loglik_grad_workspace_bytes(ctypes.byref(model.c), self.R, self.prec)
+        self.ws = torch.empty(int(self.nbytes), dtype=torch.uint8, device=dev)
+        self.loglik = torch.empty(self.R, dtype=torch.float64, device=dev)
+        self.pac = torch.empty(1, dtype=torch.float64, device=dev)
+        self.hash = model.c.hash
+        check(lib.ls_loglik_checkpoint(ctypes.byref(model.c), _p(self.rec), self.R, self.prec,
+                                       _p(self.loglik), _p(self.pac), _p(self.ws), self.nbytes,
+                                       _stream(stream)), "ls_loglik_checkpoint")
+
+    def gradient(self, stream=None):
+        """(grad_rho [L-1], grad_mu [1] or [L]) from the kept checkpoints."""
+        model = self.model
+        if model.c.hash != self.hash:
+            raise RuntimeError("the model changed since the checkpoints were taken")
+        dev = model.device
+        g_rho = torch.empty(max(model.L - 1, 1), dtype=torch.float64, device=dev)
+        g_mu = torch.empty(1 if model.mu_vec is None else model.L, dtype=torch.float64,
+                           device=dev)
+        check(_lib.load().ls_loglik_grad_adjoint(ctypes.byref(model.c), _p(self.rec), self.R,
+                                                 self.prec, _p(g_rho), _p(g_mu), _p(self.ws),
+                                                 self.nbytes, _stream(stream)),
+              "ls_loglik_grad_adjoint")
+        return g_rho[: max(model.L - 1, 0)], g_mu
+
+
 def decode(model: Model, targets: Sequence[int], prec="fp32", recipients=None,
            want: Iterable[str] = ("E",), stream=None):
     """Posterior decoding at several targets: a backward sweep that keeps
@@ -303,3 +377,43 @@ def decode(model: Model, targets: Sequence[int], prec="fp32", recipients=None,
     if fwd.l != model.L - 1:
         forward(fwd, model, model.L - 1, None, None, None, None, stream)
     return dict(P=P, E=E, fwd=fwd, bck=bck, bsnap=bsnap)
+
+
+def distance_matrices(model: Model, targets: Sequence[int], prec="fp32", window: int = 0,
+                      D: Optional[torch.Tensor] = None, stream=None):
+    """Full N x N distance matrices at the targets (eq. distmat), resident on
+    the device: recipients are decoded in windows of `window` (0: all at
+    once; the recipient windows of section 3.9), each window writing its
+    rows of the half distances straight into D ([T][N][N], allocated if
+    None) through the strided output of ls_forward; then D = E + E^T in
+    place. Returns dict(D=D, loglik=[N] per-recipient log-likelihoods)."""
+    targets = np.sort(np.asarray(targets, dtype=np.int32))
+    pc = prec_code(prec)
+    N, T, dev = model.N, len(targets), model.device
+    if T < 1 or T > LS_MAX_TARGETS:
+        raise ValueError(f"between 1 and {LS_MAX_TARGETS} targets")
+    dt = _IO_DTYPE[pc]
+    if D is None:
+        D = torch.empty((T, N, N), dtype=dt, device=dev)
+    if tuple(D.shape) != (T, N, N) or D.dtype != dt or not D.is_contiguous():
+        raise ValueError("D must be a contiguous [T][N][N] tensor of the precision's output type")
+    w = N if window <= 0 else min(int(window), N)
+    fwd = Table(model, 0, pc, np.arange(w, dtype=np.int32), stream)
+    bck = Table(model, 1, pc, np.arange(w, dtype=np.int32), stream)
+    bsnap = torch.empty((T, w, N), dtype=dt, device=dev)
+    ll = torch.empty(N, dtype=torch.float64, device=dev)
+    for r0 in range(0, N, w):
+        r1 = min(N, r0 + w)
+        rec = torch.arange(r0, r1, dtype=torch.int32, device=dev)
+        fwd.reset(model, rec, stream)
+        bck.reset(model, rec, stream)
+        R = r1 - r0
+        bs = bsnap.view(-1)[: T * R * N].view(T, R, N)
+        backward(bck, model, 0, targets, bs, stream)
+        rows = D.view(-1)[r0 * N:]  # row r0 of matrix 0 onwards
+        check(_lib.load().ls_forward(ctypes.byref(fwd.c), ctypes.byref(model.c), model.L - 1,
+                                     _i32_host(targets), T, _p(bs), None, _p(rows), N * N, N,
+                                     _stream(stream)), "ls_forward")
+        ll[r0:r1].copy_(fwd.log_scale[:R])
+    distance_symmetrise(D, D, pc, stream)
+    return dict(D=D, loglik=ll)

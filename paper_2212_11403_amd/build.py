@@ -46,13 +46,33 @@ def _headers_mtime():
     return max((os.path.getmtime(h) for h in hs), default=0.0)
 
 
+def _deps_mtime(dep_file: str):
+    """Newest modification time of the repository files a previous compile
+    read (from its make-style dependency file), or None if unknown."""
+    try:
+        text = open(dep_file).read().replace("\\\n", " ")
+    except OSError:
+        return None
+    newest = 0.0
+    for tok in text.split(":", 1)[-1].split():
+        if tok.startswith(ROOT) or not os.path.isabs(tok):
+            path = tok if os.path.isabs(tok) else os.path.join(BUILD, tok)
+            if not os.path.exists(path):
+                return None
+            newest = max(newest, os.path.getmtime(path))
+    return newest
+
+
 def _compile(src: str, force: bool, keep_asm: bool):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    newest = max(os.path.getmtime(src), _headers_mtime(), os.path.getmtime(__file__))
+    dep = obj + ".d"
+    deps = _deps_mtime(dep)
+    newest = max(os.path.getmtime(src), os.path.getmtime(__file__),
+                 _headers_mtime() if deps is None else deps)
     if not force and os.path.exists(obj) and os.path.getmtime(obj) >= newest:
         return obj, 0.0, ""
     t0 = time.time()
-    cmd = [hipcc()] + FLAGS + ["-c", src, "-o", obj + ".tmp"]
+    cmd = [hipcc()] + FLAGS + ["-MMD", "-MF", dep, "-c", src, "-o", obj + ".tmp"]
     if keep_asm and src.endswith(".hip"):
         cmd += ["-save-temps=obj"]
     r = subprocess.run(cmd, capture_output=True, text=True, cwd=BUILD)

@@ -355,7 +355,7 @@ ls_status ls_model_init(ls_model *m, void *workspace, size_t ws_bytes, void *str
     if (!muv.empty()) h = fnv1a(h, muv.data(), muv.size() * sizeof(double));
     if (m->prior) {
         // every column in [0, 1] and summing to 1 off the diagonal; the
-        // per-column sums and checksums go into the hash
+        // per-column sums and hashes of the full contents go into the hash
         double *stats = reinterpret_cast<double *>(static_cast<char *>(workspace) +
                                                    prior_stats_offset_bytes(m->N, m->L));
         std::vector<double> hs((size_t)m->N * 2);
@@ -446,12 +446,18 @@ ls_status ls_table_copy(ls_table *dst, const ls_table *src, int32_t N, void *str
 }
 
 ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t *targets,
-                     int32_t T, const void *bsnap, void *P, void *E, void *stream) {
+                     int32_t T, const void *bsnap, void *P, void *E, int64_t out_target_stride,
+                     int64_t out_row_stride, void *stream) {
     clear_stale_hip_error();
     ls_status s = check_model(m);
     if (s != LS_OK) return s;
     if ((s = check_table(fwd, m, 0)) != LS_OK) return s;
     if (t < 0 || t >= m->L || T < 0 || T > LS_MAX_TARGETS) return LS_ERR_ARG;
+    // output layout: row (k, r) of P and E starts at k ts + r rs elements
+    const int64_t rs = out_row_stride ? out_row_stride : (int64_t)m->N;
+    const int64_t ts = out_target_stride ? out_target_stride : (int64_t)fwd->R * rs;
+    if (rs < m->N || (T > 1 && ts < (int64_t)(fwd->R - 1) * rs + m->N) || ts < 0)
+        return LS_ERR_SHAPE;
     if (fwd->l >= 0 && t < fwd->l) return LS_ERR_STATE;
     if (T > 0 && !targets) return LS_ERR_ARG;
     const bool want_out = T > 0 && (P || E);
@@ -471,6 +477,8 @@ ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t 
     a.l0 = fwd->l;
     a.t = t;
     a.nt = want_out ? T : 0;
+    a.snap_ts = ts;
+    a.snap_rs = rs;
     for (int k = 0; k < a.nt; ++k) {
         a.tgt_l[k] = targets[k];
         a.tgt_out[k] = k;
@@ -493,8 +501,8 @@ ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t 
     hipError_t e = launch_sweep_chunked(fwd->prec, 0, p, a, sh, st);
     if (e != hipSuccess) return LS_ERR_DEVICE;
     if (want_out) {
-        e = lsk::launch_posterior_rows(stage, 0, bsnap, 0, fwd->recipients, fwd->R,
-                                       (int64_t)T * fwd->R, m->N, fwd->prec == LS_FP64, P, E, st);
+        e = lsk::launch_posterior_rows(stage, 0, bsnap, 0, fwd->recipients, fwd->R, T, ts, rs,
+                                       m->N, fwd->prec == LS_FP64, P, E, st);
         if (e != hipSuccess) return LS_ERR_DEVICE;
     }
     fwd->l = t;
@@ -528,6 +536,8 @@ ls_status ls_backward(ls_table *bck, const ls_model *m, int32_t t, const int32_t
     a.l0 = bck->l;
     a.t = t;
     a.nt = T;
+    a.snap_ts = (int64_t)bck->R * m->N;
+    a.snap_rs = m->N;
     for (int k = 0; k < T; ++k) {  // travel order: descending
         a.tgt_l[k] = targets[T - 1 - k];
         a.tgt_out[k] = T - 1 - k;
@@ -565,7 +575,7 @@ ls_status ls_posterior_distance(const ls_table *fwd, const ls_table *bck, const 
     if (!P && !E) return LS_OK;
     const int half = fwd->prec == LS_FP32_F16STORE;
     return dev(lsk::launch_posterior_rows(fwd->state, half, bck->state, half, fwd->recipients,
-                                          fwd->R, fwd->R, m->N, fwd->prec == LS_FP64, P, E,
+                                          fwd->R, 1, 0, m->N, m->N, fwd->prec == LS_FP64, P, E,
                                           as_stream(stream)));
 }
 
@@ -600,22 +610,31 @@ size_t ls_loglik_grad_workspace_bytes(const ls_model *m, int32_t R, ls_precision
     return lsk::grad_workspace_bytes(m->N, m->L, R, (int)prec, m->mu_vec != nullptr, nullptr);
 }
 
-ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R,
-                         ls_precision prec, double *loglik, double *pac, double *grad_rho,
-                         double *grad_mu, void *workspace, size_t ws_bytes, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// The log-likelihood and gradient entry points share their checks and set-up;
+// `phase` picks the passes (lsk::GradPhase), 0 = the log-likelihood alone.
+ls_status loglik_grad_impl(const ls_model *m, const int32_t *recipients, int32_t R,
+                           ls_precision prec, double *loglik, double *pac, double *grad_rho,
+                           double *grad_mu, void *workspace, size_t ws_bytes, void *stream,
+                           int phase) {
     clear_stale_hip_error();
     ls_status s = check_model(m);
     if (s != LS_OK) return s;
-    if (R < 1 || !valid_prec(prec) || !pac) return LS_ERR_ARG;
+    if (R < 1 || !valid_prec(prec)) return LS_ERR_ARG;
     if (!recipients && R != m->N) return LS_ERR_ARG;
-    const bool grad = grad_rho || grad_mu;
+    if (phase != lsk::kGradAdjoint && !pac) return LS_ERR_ARG;
+    const bool grad = phase & lsk::kGradAdjoint;
     if (grad && (!grad_mu || (m->L > 1 && !grad_rho))) return LS_ERR_ARG;
     const bool muv = m->mu_vec != nullptr;
     const size_t need = lsk::grad_workspace_bytes(m->N, m->L, R, (int)prec, muv, nullptr);
     if (!workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
         return LS_ERR_WORKSPACE;
+    if (phase != 0 && prec != LS_FP32 && prec != LS_FP64) return LS_ERR_UNSUPPORTED;
     Shape sh;
-    if (!choose_shape(m->N, prec, &sh, grad, m->prior != nullptr)) return LS_ERR_UNSUPPORTED;
+    if (!choose_shape(m->N, prec, &sh, phase != 0, m->prior != nullptr)) return LS_ERR_UNSUPPORTED;
     lsk::GradLayout lay;
     lsk::grad_workspace_bytes(m->N, m->L, R, (int)prec, muv, &lay);
     char *ws = static_cast<char *>(workspace);
@@ -627,18 +646,18 @@ ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R
         if (e != hipSuccess) return LS_ERR_DEVICE;
         rec = iota;
     }
-    // forward sweep of every recipient to the last variant: log F^{L-1}
-    ls_table tab;
-    s = ls_table_init(&tab, 0, prec, ws + lay.off_state, reinterpret_cast<double *>(ws + lay.off_ll),
-                      reinterpret_cast<uint32_t *>(ws + lay.off_status), rec, R, stream);
-    if (s != LS_OK) return s;
-    if (!grad) {
-        s = ls_forward(&tab, m, m->L - 1, nullptr, 0, nullptr, nullptr, nullptr, stream);
+    if (phase == 0) {
+        // forward sweep of every recipient to the last variant: log F^{L-1}
+        ls_table tab;
+        s = ls_table_init(&tab, 0, prec, ws + lay.off_state,
+                          reinterpret_cast<double *>(ws + lay.off_ll),
+                          reinterpret_cast<uint32_t *>(ws + lay.off_status), rec, R, stream);
+        if (s != LS_OK) return s;
+        s = ls_forward(&tab, m, m->L - 1, nullptr, 0, nullptr, nullptr, nullptr, 0, 0, stream);
         if (s != LS_OK) return s;
         return dev(lsk::launch_loglik_sum(reinterpret_cast<const double *>(ws + lay.off_ll), R,
                                           loglik, pac, st));
     }
-    if (prec != LS_FP32 && prec != LS_FP64) return LS_ERR_UNSUPPORTED;
     lsk::GradArgs ga;
     std::memset(&ga, 0, sizeof ga);
     ga.Hr = m->Hr;
@@ -669,7 +688,34 @@ ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R
     ga.prior = m->prior;
     ga.ws = ws;
     ga.lay = lay;
-    return dev(lsk::launch_grad(ga, (int)prec, sh, loglik, pac, grad_rho, grad_mu, st));
+    return dev(lsk::launch_grad(ga, (int)prec, sh, loglik, pac, grad_rho, grad_mu, st,
+                                static_cast<lsk::GradPhase>(phase)));
+}
+
+}  // namespace
+
+extern "C" {
+
+ls_status ls_loglik_grad(const ls_model *m, const int32_t *recipients, int32_t R,
+                         ls_precision prec, double *loglik, double *pac, double *grad_rho,
+                         double *grad_mu, void *workspace, size_t ws_bytes, void *stream) {
+    const bool grad = grad_rho || grad_mu;
+    return loglik_grad_impl(m, recipients, R, prec, loglik, pac, grad_rho, grad_mu, workspace,
+                            ws_bytes, stream, grad ? lsk::kGradBoth : 0);
+}
+
+ls_status ls_loglik_checkpoint(const ls_model *m, const int32_t *recipients, int32_t R,
+                               ls_precision prec, double *loglik, double *pac, void *workspace,
+                               size_t ws_bytes, void *stream) {
+    return loglik_grad_impl(m, recipients, R, prec, loglik, pac, nullptr, nullptr, workspace,
+                            ws_bytes, stream, lsk::kGradForward);
+}
+
+ls_status ls_loglik_grad_adjoint(const ls_model *m, const int32_t *recipients, int32_t R,
+                                 ls_precision prec, double *grad_rho, double *grad_mu,
+                                 void *workspace, size_t ws_bytes, void *stream) {
+    return loglik_grad_impl(m, recipients, R, prec, nullptr, nullptr, grad_rho, grad_mu,
+                            workspace, ws_bytes, stream, lsk::kGradAdjoint);
 }
 
 ls_status ls_status_check(const uint32_t *status, int32_t R, void *stream) {
@@ -688,11 +734,11 @@ ls_status ls_status_check(const uint32_t *status, int32_t R, void *stream) {
     return LS_OK;
 }
 
-ls_status ls_kernel_shape(int32_t N, ls_precision prec, int32_t *slots_per_wave,
-                          int32_t *waves_per_recipient) {
+ls_status ls_kernel_shape(int32_t N, ls_precision prec, int32_t with_prior,
+                          int32_t *slots_per_wave, int32_t *waves_per_recipient) {
     if (N < 2 || !valid_prec(prec)) return LS_ERR_ARG;
     Shape sh;
-    if (!choose_shape(N, prec, &sh)) return LS_ERR_UNSUPPORTED;
+    if (!choose_shape(N, prec, &sh, false, with_prior != 0)) return LS_ERR_UNSUPPORTED;
     if (slots_per_wave) *slots_per_wave = sh.nslot;
     if (waves_per_recipient) *waves_per_recipient = sh.nwaves;
     return LS_OK;

@@ -119,8 +119,10 @@ sum_rows_kernel(const double *__restrict__ grow, int32_t R, int32_t rows, double
 // table also gives log P per recipient), then, segment by segment from the
 // last, a forward recompute of the segment from its checkpoint (sweep kernel
 // in its keep-alpha mode) followed by the adjoint pass (ls_grad_kernel.h).
+// The two halves are separate calls (GradPhase), so that a caller can keep
+// the checkpoints of a log-likelihood evaluation and run the adjoint later.
 hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, double *pac,
-                       double *grad_rho, double *grad_mu, hipStream_t st) {
+                       double *grad_rho, double *grad_mu, hipStream_t st, GradPhase phase) {
     const GradLayout &Ly = ga.lay;
     char *ws = ga.ws;
     const int64_t RN = (int64_t)ga.R * ga.N;
@@ -162,6 +164,8 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
         a.bmul = 1.0 / (double)(ga.N - 1);
         a.log_off = em.log_unit;
         a.c_off = (int64_t)((Ly.off_cval - Ly.off_seg) / es);
+        a.snap_ts = RN;
+        a.snap_rs = ga.N;
         for (int k = 0; k < nt; ++k) {
             a.tgt_l[k] = tl[2 * k];
             a.tgt_out[k] = tl[2 * k + 1];
@@ -174,29 +178,33 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
         return prec == 0 ? launch_sweep_f64_fwd(p, a, ga.fwd_shape, st)
                          : launch_sweep_f32_fwd(p, a, ga.fwd_shape, st);
     };
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ws + Ly.off_status), 0u, ga.R, st);
-    if (e != hipSuccess) return e;
-    // 1. forward with checkpoints at l = k * seg; ll = log F^{L-1}. It runs
-    // with the sweep's own shape and in the launches a plain forward sweep
-    // makes (at most ga.chunk variants each, resuming from the table), so
-    // log P is bit-identical to that of the log-likelihood alone. A launch
-    // holds at most chunk / seg + 1 <= sqrt(chunk) + 1 checkpoints (with an
-    // oversized chunk, a launch ends at its 256th checkpoint).
     void *fstate = ws + Ly.off_state;
     double *ll = reinterpret_cast<double *>(ws + Ly.off_ll);
-    std::vector<int32_t> tl(2 * kMaxTargets);
-    int l0 = -1, knext = 0;
-    while (l0 < ga.L - 1) {
-        int t = std::min(ga.L - 1, (l0 < 0 ? 0 : l0) + ga.chunk);
-        int nt = 0;
-        for (; knext < ga.nseg && knext * ga.seg <= t && nt < kMaxTargets; ++knext, ++nt) {
-            tl[2 * nt] = knext * ga.seg;
-            tl[2 * nt + 1] = knext;
-        }
-        if (knext < ga.nseg && knext * ga.seg <= t) t = tl[2 * (nt - 1)];
-        e = sweep(0, l0, t, tl.data(), nt, fstate, ws + Ly.off_ckpt, ll);
+    hipError_t e = hipSuccess;
+    if (phase != kGradAdjoint) {
+        e = launch_fill_u32(reinterpret_cast<uint32_t *>(ws + Ly.off_status), 0u, ga.R, st);
         if (e != hipSuccess) return e;
-        l0 = t;
+        // 1. forward with checkpoints at l = k * seg; ll = log F^{L-1}. It runs
+        // with the sweep's own shape and in the launches a plain forward sweep
+        // makes (at most ga.chunk variants each, resuming from the table), so
+        // log P is bit-identical to that of the log-likelihood alone. A launch
+        // holds at most chunk / seg + 1 <= sqrt(chunk) + 1 checkpoints (with an
+        // oversized chunk, a launch ends at its 256th checkpoint).
+        std::vector<int32_t> tl(2 * kMaxTargets);
+        int l0 = -1, knext = 0;
+        while (l0 < ga.L - 1) {
+            int t = std::min(ga.L - 1, (l0 < 0 ? 0 : l0) + ga.chunk);
+            int nt = 0;
+            for (; knext < ga.nseg && knext * ga.seg <= t && nt < kMaxTargets; ++knext, ++nt) {
+                tl[2 * nt] = knext * ga.seg;
+                tl[2 * nt + 1] = knext;
+            }
+            if (knext < ga.nseg && knext * ga.seg <= t) t = tl[2 * (nt - 1)];
+            e = sweep(0, l0, t, tl.data(), nt, fstate, ws + Ly.off_ckpt, ll);
+            if (e != hipSuccess) return e;
+            l0 = t;
+        }
+        if (phase == kGradForward) return launch_loglik_sum(ll, ga.R, loglik, pac, st);
     }
     // 2. segments from the last to the first
     double *scratch = reinterpret_cast<double *>(ws + Ly.off_lsc);
@@ -244,6 +252,7 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
         hipLaunchKernelGGL(sum_rows_kernel, dim3(1), dim3(64), 0, st,
                            reinterpret_cast<const double *>(ws + Ly.off_gmu), ga.R, 1, grad_mu);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (phase == kGradAdjoint) return hipSuccess;
     return launch_loglik_sum(ll, ga.R, loglik, pac, st);
 }
 

@@ -54,6 +54,8 @@ struct SweepArgs {
                           // plus the emission unit's log (see sweep_emissions)
     int64_t c_off;        // keep-alpha mode (gradient recompute): element offset, from
                           // the snapshot array, of the [t - l0][R] c of each step
+    int64_t snap_ts;      // elements between the snapshot rows of consecutive targets
+    int64_t snap_rs;      // elements between the snapshot rows of consecutive recipients
     int32_t tgt_l[kMaxTargets];    // variant of each visited target, travel order
     int32_t tgt_out[kMaxTargets];  // its index k in the [T] output arrays
 };
@@ -203,8 +205,8 @@ hipError_t launch_emission_tables(const double *mu_vec, int32_t L, double *em64,
                                   double *lu_prefix, hipStream_t st);
 // Per row i of a prior matrix ([N][N], row i = prior column of recipient i):
 // out[2i] = sum of the row without its diagonal (NaN if any entry is
-// negative, above 1 or not finite), out[2i+1] = sum_j (j+1) row[j] (a
-// checksum), both in a fixed order (ls_misc.hip).
+// negative, above 1 or not finite), in a fixed order; out[2i+1] = the bits
+// of a 64-bit hash of the whole row (ls_misc.hip).
 hipError_t launch_prior_stats(const double *prior, int32_t N, double *out, hipStream_t st);
 // Recombination map (eq. rho) and its chain rule (ls_misc.hip)
 hipError_t launch_calc_rho(const double *cM, int32_t n, double s, double gamma, double *rho,
@@ -213,13 +215,16 @@ hipError_t launch_rho_map_grad(const double *cM, int32_t n, double s, double gam
                                const double *g, double *out, hipStream_t st);
 hipError_t launch_symmetrise(const void *E, void *D, int32_t N, int32_t T, int is_f64,
                              hipStream_t st);
-// Posterior and half distances for `rows` rows of length N: row q holds the
-// forward vector alpha[q] and backward vector beta[q] of recipient
-// recips[q % R]. P and E may be null; either may alias alpha (in place).
-// alpha/beta/P/E element types follow `prec` (half tables: ST = half).
+// Posterior and half distances for T x R rows of length N: row (k, r) pairs
+// the forward vector at alpha + k ts + r rs with the backward vector at
+// beta + (k R + r) N for recipient recips[r], and writes P and E at the
+// same offsets as alpha (elements). P and E may be null; either may alias
+// alpha (in place). alpha/beta/P/E element types follow `is_f64` and the
+// half flags (half tables hold IEEE half; P and E are then FP32).
 hipError_t launch_posterior_rows(const void *alpha, int alpha_half, const void *beta,
-                                 int beta_half, const int32_t *recips, int32_t R, int64_t rows,
-                                 int32_t N, int is_f64, void *P, void *E, hipStream_t st);
+                                 int beta_half, const int32_t *recips, int32_t R, int32_t T,
+                                 int64_t ts, int64_t rs, int32_t N, int is_f64, void *P, void *E,
+                                 hipStream_t st);
 
 // Log-likelihood and gradient (ls_grad.hip).
 // Workspace layout of ls_loglik_grad (byte offsets, 256-byte aligned).
@@ -269,7 +274,11 @@ hipError_t launch_iota(int32_t *p, int32_t n, hipStream_t st);
 // loglik[r] = ll[r] (if loglik != null) and *pac = sum_r ll[r] in index order
 hipError_t launch_loglik_sum(const double *ll, int32_t R, double *loglik, double *pac,
                              hipStream_t st);
+// What launch_grad runs: the checkpointing forward and the log-likelihood
+// sum, the adjoint pass over checkpoints a previous kGradForward call left
+// in the workspace, or both.
+enum GradPhase { kGradForward = 1, kGradAdjoint = 2, kGradBoth = 3 };
 hipError_t launch_grad(const GradArgs &a, int prec, Shape shape, double *loglik, double *pac,
-                       double *grad_rho, double *grad_mu, hipStream_t st);
+                       double *grad_rho, double *grad_mu, hipStream_t st, GradPhase phase);
 
 }  // namespace lsk

@@ -101,7 +101,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------------------------
-// Posterior rows. One workgroup per row q (recipient recips[q % R]):
+// Posterior rows. One workgroup per row (k, r) = (blockIdx.y, blockIdx.x) of
+// recipient i = recips[r]; the forward row and the outputs sit at
+// k ts + r rs, the backward row at (k R + r) N:
 //   Z = sum_j alpha_j beta_j,  p_j = alpha_j beta_j / Z (eps for all j != i
 //   when Z == 0), E_j = -log(max(p_j, eps)) / 2, p_i = E_i = 0.
 // The row is read twice (once for Z, once for the outputs), so P or E may
@@ -109,12 +111,14 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 template <class T, class A, class B, class O>
 __global__ void __launch_bounds__(256)
 posterior_rows_kernel(const A *alpha, const B *__restrict__ beta, const int32_t *__restrict__ recips,
-                      int32_t R, int32_t N, O *P, O *E) {
+                      int32_t R, int64_t ts, int64_t rs, int32_t N, O *P, O *E) {
     __shared__ T red[256 / 64];
-    const int64_t q = blockIdx.x;
-    const int i = recips[q % R];
-    const A *ar = alpha + q * N;
-    const B *br = beta + q * N;
+    const int r = blockIdx.x;
+    const int64_t k = blockIdx.y;
+    const int i = recips[r];
+    const int64_t off = k * ts + (int64_t)r * rs;
+    const A *ar = alpha + off;
+    const B *br = beta + (k * R + r) * (int64_t)N;
     T z = 0;
     for (int j = threadIdx.x; j < N; j += 256) z = fma((T)ar[j], (T)br[j], z);
     z = wave_sum(z);
@@ -124,8 +128,8 @@ posterior_rows_kernel(const A *alpha, const B *__restrict__ beta, const int32_t 
     const T Z = (red[0] + red[1]) + (red[2] + red[3]);
     const T eps = (T)2.220446049250313080847e-16;
     const T invZ = (T)1 / Z;
-    O *Pr = P ? P + q * N : nullptr;
-    O *Er = E ? E + q * N : nullptr;
+    O *Pr = P ? P + off : nullptr;
+    O *Er = E ? E + off : nullptr;
     for (int j = threadIdx.x; j < N; j += 256) {
         T p = (Z == (T)0) ? eps : (T)ar[j] * (T)br[j] * invZ;
         if (j == i) p = 0;
@@ -137,26 +141,29 @@ posterior_rows_kernel(const A *alpha, const B *__restrict__ beta, const int32_t 
 }
 
 // The same rows with the products alpha_j beta_j held in registers, for
-// N <= 1024 K W (W = 16 / sizeof(T) elements per 16-byte vector, N a
-// multiple of W): alpha and beta are read once, with 16-byte loads, and P / E
-// are written with streaming stores. One workgroup of 1024 threads per row;
-// each thread keeps the products of the entries it writes.
+// N <= 1024 K W (W = 16 / sizeof(T) elements per 16-byte vector, N, ts and
+// rs multiples of W): alpha and beta are read once, with 16-byte loads, and
+// P / E are written with streaming stores. One workgroup of 1024 threads per
+// row; each thread keeps the products of the entries it writes.
 template <class T, int K>
 __global__ void __launch_bounds__(1024)
 posterior_rows_reg_kernel(const T *alpha, const T *__restrict__ beta,
-                          const int32_t *__restrict__ recips, int32_t R, int32_t N, T *P, T *E) {
+                          const int32_t *__restrict__ recips, int32_t R, int64_t ts, int64_t rs,
+                          int32_t N, T *P, T *E) {
     using V = typename std::conditional<sizeof(T) == 4, f32x4, f64x2>::type;
     constexpr int W = 16 / (int)sizeof(T);
     __shared__ T red[16];
-    const int64_t q = blockIdx.x;
-    const int i = recips[q % R];
-    const T *ar = alpha + q * N;
-    const T *br = beta + q * N;
+    const int r = blockIdx.x;
+    const int64_t k = blockIdx.y;
+    const int i = recips[r];
+    const int64_t off = k * ts + (int64_t)r * rs;
+    const T *ar = alpha + off;
+    const T *br = beta + (k * R + r) * (int64_t)N;
     T w[K][W];
     T z = 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int j0 = ((int)threadIdx.x + 1024 * k) * W;
+    for (int q = 0; q < K; ++q) {
+        const int j0 = ((int)threadIdx.x + 1024 * q) * W;
         V a = {}, b = {};
         if (j0 < N) {
             a = *reinterpret_cast<const V *>(ar + j0);
@@ -166,8 +173,8 @@ posterior_rows_reg_kernel(const T *alpha, const T *__restrict__ beta,
         const T *xb = reinterpret_cast<const T *>(&b);
 #pragma unroll
         for (int e = 0; e < W; ++e) {
-            w[k][e] = xa[e] * xb[e];
-            z += w[k][e];
+            w[q][e] = xa[e] * xb[e];
+            z += w[q][e];
         }
     }
     z = wave_sum(z);
@@ -176,19 +183,19 @@ posterior_rows_reg_kernel(const T *alpha, const T *__restrict__ beta,
     __syncthreads();
     T t[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) t[k] = red[k];
+    for (int q = 0; q < 16; ++q) t[q] = red[q];
 #pragma unroll
     for (int h = 1; h < 16; h *= 2)
 #pragma unroll
-        for (int k = 0; k + h < 16; k += 2 * h) t[k] += t[k + h];
+        for (int q = 0; q + h < 16; q += 2 * h) t[q] += t[q + h];
     const T Z = t[0];
     const T eps = (T)2.220446049250313080847e-16;
     const T invZ = (T)1 / Z;
-    T *Pr = P ? P + q * N : nullptr;
-    T *Er = E ? E + q * N : nullptr;
+    T *Pr = P ? P + off : nullptr;
+    T *Er = E ? E + off : nullptr;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int j0 = ((int)threadIdx.x + 1024 * k) * W;
+    for (int q = 0; q < K; ++q) {
+        const int j0 = ((int)threadIdx.x + 1024 * q) * W;
         if (j0 >= N) continue;
         V vp, ve;
         T *xp = reinterpret_cast<T *>(&vp);
@@ -196,7 +203,7 @@ posterior_rows_reg_kernel(const T *alpha, const T *__restrict__ beta,
 #pragma unroll
         for (int e = 0; e < W; ++e) {
             const int j = j0 + e;
-            T pv = (Z == (T)0) ? eps : w[k][e] * invZ;
+            T pv = (Z == (T)0) ? eps : w[q][e] * invZ;
             if (j == i) pv = 0;
             const T qv = (pv < eps) ? eps : pv;  // NaN passes through
             xp[e] = pv;
@@ -208,39 +215,43 @@ posterior_rows_reg_kernel(const T *alpha, const T *__restrict__ beta,
 }
 
 hipError_t launch_posterior_rows(const void *alpha, int alpha_half, const void *beta,
-                                 int beta_half, const int32_t *recips, int32_t R, int64_t rows,
-                                 int32_t N, int is_f64, void *P, void *E, hipStream_t st) {
-    if (rows <= 0) return hipSuccess;
-    const dim3 grid((unsigned)rows), block(256);
-    // rows that fit the register kernel: full-precision inputs, N a multiple
-    // of the vector width, at most 16 elements per thread, 16-byte aligned
+                                 int beta_half, const int32_t *recips, int32_t R, int32_t T,
+                                 int64_t ts, int64_t rs, int32_t N, int is_f64, void *P, void *E,
+                                 hipStream_t st) {
+    if (R <= 0 || T <= 0) return hipSuccess;
+    if (T > 65535) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)R, (unsigned)T), block(256);
+    // rows that fit the register kernel: full-precision inputs, N and the
+    // strides multiples of the vector width, at most 16 elements per thread,
+    // 16-byte aligned
     auto aligned = [](const void *x) { return (reinterpret_cast<uintptr_t>(x) & 15) == 0; };
     const int w = is_f64 ? 2 : 4;
-    const bool reg = !alpha_half && !beta_half && N % w == 0 && N <= 1024 * 16 &&
-                     aligned(alpha) && aligned(beta) && aligned(P) && aligned(E);
+    const bool reg = !alpha_half && !beta_half && N % w == 0 && ts % w == 0 && rs % w == 0 &&
+                     N <= 1024 * 16 && aligned(alpha) && aligned(beta) && aligned(P) &&
+                     aligned(E);
     if (reg) {
         if (is_f64)
             hipLaunchKernelGGL((posterior_rows_reg_kernel<double, 8>), grid, dim3(1024), 0, st,
-                               (const double *)alpha, (const double *)beta, recips, R, N,
+                               (const double *)alpha, (const double *)beta, recips, R, ts, rs, N,
                                (double *)P, (double *)E);
         else
             hipLaunchKernelGGL((posterior_rows_reg_kernel<float, 4>), grid, dim3(1024), 0, st,
-                               (const float *)alpha, (const float *)beta, recips, R, N,
+                               (const float *)alpha, (const float *)beta, recips, R, ts, rs, N,
                                (float *)P, (float *)E);
         return hipGetLastError();
     }
     if (is_f64) {
         hipLaunchKernelGGL((posterior_rows_kernel<double, double, double, double>), grid, block, 0,
-                           st, (const double *)alpha, (const double *)beta, recips, R, N,
+                           st, (const double *)alpha, (const double *)beta, recips, R, ts, rs, N,
                            (double *)P, (double *)E);
     } else if (alpha_half && beta_half) {
         hipLaunchKernelGGL((posterior_rows_kernel<float, _Float16, _Float16, float>), grid, block,
-                           0, st, (const _Float16 *)alpha, (const _Float16 *)beta, recips, R, N,
-                           (float *)P, (float *)E);
+                           0, st, (const _Float16 *)alpha, (const _Float16 *)beta, recips, R, ts,
+                           rs, N, (float *)P, (float *)E);
     } else {
         hipLaunchKernelGGL((posterior_rows_kernel<float, float, float, float>), grid, block, 0, st,
-                           (const float *)alpha, (const float *)beta, recips, R, N, (float *)P,
-                           (float *)E);
+                           (const float *)alpha, (const float *)beta, recips, R, ts, rs, N,
+                           (float *)P, (float *)E);
     }
     return hipGetLastError();
 }
@@ -432,36 +443,50 @@ hipError_t launch_emission_tables(const double *mu_vec, int32_t L, double *em64,
 
 // ---------------------------------------------------------------------------
 // Checks of a prior copying matrix (one workgroup per recipient's column):
-// strided per-thread sums in index order, then a fixed tree.
+// the sum of the column without its diagonal (NaN if any entry is negative,
+// above 1 or not finite), strided per-thread sums in index order, then a
+// fixed tree; and a 64-bit hash of the whole column: the wrap-around sum
+// over entries of a mixed (value bits, index) word. Integer sums do not
+// depend on their order, and two columns that differ in any entry (a
+// change that keeps every moment of the column included) differ in the
+// hash with overwhelming probability.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
 __global__ void __launch_bounds__(256)
 prior_stats_kernel(const double *__restrict__ prior, int32_t N, double *__restrict__ out) {
-    __shared__ double ps[256], pw[256];
+    __shared__ double ps[256];
+    __shared__ uint64_t ph[256];
     __shared__ int pbad[256];
     const int i = blockIdx.x;
     const double *row = prior + (int64_t)i * N;
-    double s = 0.0, w = 0.0;
+    double s = 0.0;
+    uint64_t h = 0;
     int bad = 0;
     for (int j = threadIdx.x; j < N; j += 256) {
         const double x = row[j];
         if (!(x >= 0.0 && x <= 1.0)) bad = 1;
         if (j != i) s += x;
-        w += (double)(j + 1) * x;
+        h += mix64((uint64_t)__double_as_longlong(x) ^ ((uint64_t)(j + 1) * 0x9e3779b97f4a7c15ull));
     }
     ps[threadIdx.x] = s;
-    pw[threadIdx.x] = w;
+    ph[threadIdx.x] = h;
     pbad[threadIdx.x] = bad;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-            ps[threadIdx.x] += ps[threadIdx.x + h];
-            pw[threadIdx.x] += pw[threadIdx.x + h];
-            pbad[threadIdx.x] |= pbad[threadIdx.x + h];
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) {
+            ps[threadIdx.x] += ps[threadIdx.x + k];
+            ph[threadIdx.x] += ph[threadIdx.x + k];
+            pbad[threadIdx.x] |= pbad[threadIdx.x + k];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         out[2 * i] = pbad[0] ? __builtin_nan("") : ps[0];
-        out[2 * i + 1] = pw[0];
+        out[2 * i + 1] = __longlong_as_double((long long)ph[0]);
     }
 }
 

@@ -344,7 +344,7 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
         }
     };
     auto snapshot = [&]() __attribute__((always_inline)) {
-        IO *dst = snap + ((int64_t)a.tgt_out[kt] * a.R + r) * N;
+        IO *dst = snap + (int64_t)a.tgt_out[kt] * a.snap_ts + (int64_t)r * a.snap_rs;
         store_row(dst, (T)a.inv_kappa);
         ++kt;
     };

@@ -77,8 +77,8 @@ def test_validation_errors_before_any_device_work(lib):
     m.N, m.L = 1, 5
     assert lib.ls_model_init(ctypes.byref(m), None, 0, None) == 1
     t = LsTable()
-    assert lib.ls_forward(None, ctypes.byref(m), 0, None, 0, None, None, None, None) == 1
-    assert lib.ls_forward(ctypes.byref(t), None, 0, None, 0, None, None, None, None) == 1
+    assert lib.ls_forward(None, ctypes.byref(m), 0, None, 0, None, None, None, 0, 0, None) == 1
+    assert lib.ls_forward(ctypes.byref(t), None, 0, None, 0, None, None, None, 0, 0, None) == 1
     assert lib.ls_table_init(ctypes.byref(t), 2, 1, None, None, None, None, 0, None) == 1
     assert lib.ls_distance_symmetrise(None, None, 3, 1, 1, None) == 1
     assert lib.ls_status_check(None, 1, None) == 1
@@ -90,13 +90,17 @@ def test_kernel_shapes_cover_every_size(lib):
     a, b = ctypes.c_int32(), ctypes.c_int32()
     limits = {0: 45000, 1: 100000, 2: 100000}
     for prec, nmax in limits.items():
-        for N in list(range(2, 3000)) + list(range(3000, nmax + 1, 997)) + [nmax]:
-            rc = lib.ls_kernel_shape(N, prec, ctypes.byref(a), ctypes.byref(b))
-            assert rc == 0, (prec, N)
-            ns, nw = a.value, b.value
-            K = min(ns, 4)
-            NW, NF = (N + 63) // 64, N // 64
-            assert nw * (ns - K) <= NF and nw * ns >= NW, (prec, N, ns, nw)
+        for prior in (0, 1):
+            top = nmax if not prior else nmax // 2
+            for N in list(range(2, 3000, 1 + 6 * prior)) + list(range(3000, top + 1, 997)) + [top]:
+                rc = lib.ls_kernel_shape(N, prec, prior, ctypes.byref(a), ctypes.byref(b))
+                assert rc == 0, (prec, prior, N)
+                ns, nw = a.value, b.value
+                K = min(ns, 4)
+                NW, NF = (N + 63) // 64, N // 64
+                assert nw * (ns - K) <= NF and nw * ns >= NW, (prec, prior, N, ns, nw)
+    assert lib.ls_kernel_shape(1, 1, 0, ctypes.byref(a), ctypes.byref(b)) == 1
+    assert lib.ls_kernel_shape(100, 7, 0, ctypes.byref(a), ctypes.byref(b)) == 1
 
 
 @pytest.mark.parametrize("N,L,R", [(2000, 50_000, 2000), (10_000, 100_000, 64), (300, 5000, 300)])

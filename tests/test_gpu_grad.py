@@ -224,3 +224,38 @@ def test_differentiation_workload_sampled(ls):
         rm[l] -= h
         fd = (pac(rp) - pac(rm)) / (2 * h)
         assert abs(fd - gr32[l]) <= 1e-4 * gmax, (l, fd, gr32[l])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_autograd_bit_identical_to_loglik_grad(ls, prec):
+    """PACLoglik keeps the checkpoints of its forward and runs only the
+    adjoint in its backward: PAC and gradient are the same bits as one
+    ls_loglik_grad call. With H a device tensor the model is reused across
+    applies (parameters set again in place), a second apply at other rho
+    and mu again matches a fresh model bit for bit."""
+    import torch
+    N, L = 300, 700
+    H, rho, mu = _case(N, L, seed=31)
+    Hd = torch.from_numpy(np.ascontiguousarray(H).view(np.int32)).cuda()
+    for step, (rr, mm) in enumerate(((rho, mu), (rho * 0.7, mu * 1.3))):
+        r = torch.tensor(rr, dtype=torch.float64, device="cuda", requires_grad=True)
+        m_ = torch.tensor(mm, dtype=torch.float64, device="cuda", requires_grad=True)
+        pac = ls.PACLoglik.apply(r, m_, Hd, N, prec)
+        pac.backward()
+        ref = ls.loglik_grad(ls.Model(H, N, rr, mm), None, prec, grad=True)
+        assert pac.item() == ref["pac"].item(), step
+        assert torch.equal(r.grad, ref["grad_rho"]), step
+        assert m_.grad.item() == ref["grad_mu"].item(), step
+
+
+def test_checkpoints_refuse_a_changed_model(ls):
+    N, L = 80, 90
+    H, rho, mu = _case(N, L, seed=5)
+    m = ls.Model(H, N, rho, mu)
+    from paper_2212_11403_amd import api
+    ck = api.Checkpoints(m, None, "fp32")
+    g1 = ck.gradient()
+    m.update(rho * 0.5, mu)
+    with pytest.raises(RuntimeError):
+        ck.gradient()
+    assert g1[0].shape[0] == L - 1
