@@ -1,15 +1,24 @@
 """Benchmark: LS forward+backward cell updates per second (N^2 L / s) on one
 MI355X, FP32-scaled sweep, with the plain FP64 path measured beside it.
 
-Workload (one "step" = the whole hot path over one batch): N = 10,000
-mosaic haplotypes of 200 founders, L = 100,000 variants, mu = 1e-4, rho from
-Exp(mean 1e-3) spacings; a backward sweep that keeps beta at 100 evenly
-spaced targets, a forward sweep that turns alpha and beta into posteriors
-and half distances at those targets, and the symmetrisation into 100 full
-N x N FP32 distance matrices (40 GB resident in HBM). Inputs are generated
-before the timed region and are resident on the device.
+Workload of the timed step: N = 10,000 mosaic haplotypes of 200 founders,
+L = 100,000 variants, mu = 1e-4, rho from Exp(mean 1e-3) spacings; a
+backward sweep that keeps beta at 100 evenly spaced targets, a forward sweep
+that turns alpha and beta into posteriors and half distances at those
+targets, and the symmetrisation into 100 full N x N FP32 distance matrices
+(40 GB resident in HBM). Inputs are generated before the timed region and are
+resident on the device.
 
-Prints one JSON line (see the README of this repository for the fields).
+Outside the timed region the same line reports: the FP64 step; the FP32
+posterior error against FP64 over every recipient and target; the FP64 CPU
+oracle's rate (all host cores and one core) and the FP32 error against it on
+the oracle's sample; the gradient workload (N = 2,000, L = 50,000: PAC and its
+gradient for all recipients, error against the oracle on 256 recipients); the
+large workload (N = 100,000, L = 10,000: five resident 100k x 100k FP32
+distance matrices from recipient windows, error against the oracle on 64
+recipients); and the FP16-stored precision on the benchmark workload.
+
+Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -25,15 +34,22 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP32 vector peak in lane-operations/s: 157.3 TFLOP/s counts an FMA as two
-# flops, i.e. 78.6e12 FP32 lane-operations/s = 256 CUs x 4 SIMDs x 32 lanes x
-# 2.4 GHz (each SIMD issues two wave64 FP32 instructions per four cycles,
-# which the SQ_ACTIVE_INST_VALU2 counter shows happening in this kernel).
-VALU_PEAK = 256 * 4 * 32 * 2.4e9
-# FP64 vector peak: 78.6 TFLOP/s, i.e. 39.3e12 FP64 FMA lane-operations/s.
-VALU_PEAK_F64 = 256 * 4 * 16 * 2.4e9
-OPS_PER_CELL = 4                  # emission select, FMA, MUL, ADD per cell per direction
-SWEEP_CHUNK = 2048                # variants per sweep launch (the library splits longer sweeps)
+# Published MI355X vector peaks (dense, no sparsity): FP32 157.3 TFLOP/s,
+# FP64 78.6 TFLOP/s, an FMA counting as two flops.
+FP32_PEAK = 157.3e12
+FP64_PEAK = 78.6e12
+# Algorithmic flops per cell and direction: FMA (2) + MUL + ADD; the emission
+# select is not a flop.
+FLOPS_PER_CELL = 4
+# Issue ceiling of the VALU in FP32 lane-operations/s: the FP32 peak above at
+# two flops per FMA, i.e. 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz (two wave64
+# instructions per SIMD every four cycles; one wave64 instruction per four
+# cycles would be half of it). The sweep issues 4 lane-operations per cell:
+# select, FMA, MUL, ADD.
+ISSUE_PEAK = 256 * 4 * 32 * 2.4e9
+ISSUE_OPS_PER_CELL = 4
+HBM_PEAK = 8.0e12
+SWEEP_CHUNK = 2048  # variants per sweep launch (the library splits longer sweeps)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_bwd_fp32_c2_traffic.txt")
 SWEEP_SOURCES = ["ls_sweep.h", "ls_device.h", "ls_internal.h", "ls_sweep_f32_bwd.hip"]
 
@@ -69,8 +85,8 @@ def measured_traffic(shape):
 
 
 def copy_calibration():
-    """A plain 1 GiB device-to-device copy, for scaling the FETCH_SIZE and
-    WRITE_SIZE counters (profiled under rocprofv3 --pmc)."""
+    """A plain elementwise copy over 2 GiB buffers, for scaling the FETCH_SIZE
+    and WRITE_SIZE counters (profiled under rocprofv3 --pmc)."""
     import torch
     n = 1 << 29  # 2 GiB per buffer, well above the 256 MB last-level cache
     src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -83,34 +99,158 @@ def copy_calibration():
           flush=True)
 
 
-def stream_probe():
-    """Practical HBM rates of plain streaming kernels (torch elementwise ops
-    over 4 GiB, event-timed), the yardstick for the HBM-bound kernels."""
-    import torch
-    n = 1 << 30
-    x = torch.rand(n, device="cuda")
-    y = torch.empty_like(x)
-
-    def rate(f, nbytes, reps=5):
-        f()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            f()
-        e1.record()
-        torch.cuda.synchronize()
-        return nbytes / (e0.elapsed_time(e1) / reps / 1e3) / 1e12
-
-    out = {"unit": "TB/s",
-           "read_write_in_place": rate(lambda: x.mul_(1.0000001), 8 * n),
-           "read_write": rate(lambda: torch.mul(x, 1.0000001, out=y), 8 * n),
-           "write_only": rate(lambda: y.fill_(0.5), 4 * n)}
-    print(json.dumps(out), flush=True)
-
-
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+class Timer:
+    """HIP events on the stream the library launches on (torch's current
+    stream, handed to every call)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.e = [torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+
+    def __enter__(self):
+        self.e[0].record(self.torch.cuda.current_stream())
+        return self
+
+    def __exit__(self, *a):
+        self.e[1].record(self.torch.cuda.current_stream())
+
+    def ms(self):
+        self.e[1].synchronize()
+        return self.e[0].elapsed_time(self.e[1])
+
+
+def oracle_rate(oracle, x, nthreads, count, seed):
+    """The oracle (FP64 C) on `count` seeded recipients over the full
+    workload: forward, backward and posteriors at every target."""
+    from lsinputs import seeded_recipients
+    N, L = x["N"], x["L"]
+    sample = seeded_recipients(N, count, seed=seed)
+    t0 = time.perf_counter()
+    ref = oracle.run_pass(x["H"], N, L, x["rho"], x["mu"], sample, x["targets"], want=("P",),
+                          nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    return len(sample) * float(N) * L / dt, dt, sample, ref
+
+
+def c2_accuracy_all(ls, torch, model, targets, N, window=50):
+    """Max abs posterior error of the FP32 sweep against the FP64 sweep over
+    every recipient and target (decoded in windows of targets, compared on
+    the device)."""
+    err = 0.0
+    ll_err = 0.0
+    for lo in range(0, len(targets), window):
+        tg = targets[lo:lo + window]
+        p32 = ls.decode(model, tg, "fp32", want=("P",))
+        ll32 = p32["fwd"].log_scale.clone()
+        p32 = p32["P"]
+        out64 = ls.decode(model, tg, "fp64", want=("P",))
+        p64 = out64["P"]
+        for k in range(len(tg)):
+            err = max(err, float((p32[k].double() - p64[k]).abs().max().item()))
+        ll64 = out64["fwd"].log_scale
+        ll_err = max(ll_err, float(((ll32 - ll64).abs() / ll64.abs()).max().item()))
+        del p32, p64, out64
+        torch.cuda.empty_cache()
+    return err, ll_err
+
+
+def gradient_workload(ls, torch, oracle, nthreads, reps=3):
+    """PAC and its gradient for every recipient of the gradient workload
+    (N = 2,000, L = 50,000), FP32 and FP64, timed with HIP events; error of
+    both against the oracle's exact score on 256 seeded recipients."""
+    from lsinputs import make_inputs, seeded_recipients
+    x = make_inputs("c4")
+    N, L, rho, mu = x["N"], x["L"], x["rho"], x["mu"]
+    m = ls.Model(x["H"], N, rho, mu)
+    out = {"workload": f"N={N}, L={L}, gradient w.r.t. {L - 1} rho_l and mu, all {N} recipients"}
+    for prec in ("fp32", "fp64"):
+        ls.loglik_grad(m, None, prec, grad=True)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            with Timer(torch) as t:
+                ls.loglik_grad(m, None, prec, grad=True)
+            ts.append(t.ms())
+        with Timer(torch) as t:
+            ls.loglik_grad(m, None, prec, grad=False)
+        out[f"{prec}_gradient_ms"] = float(np.mean(ts))
+        out[f"{prec}_loglik_only_ms"] = t.ms()
+    rec = seeded_recipients(N, 256, seed=404)
+    t0 = time.perf_counter()
+    ref = oracle.run_gradient(x["H"], N, L, rho, mu, rec, nthreads=nthreads)
+    out["oracle_seconds_256"] = time.perf_counter() - t0
+    gr = ref["grad_rho"].sum(axis=0)
+    gm = ref["grad_mu"].sum()
+    ll = ref["loglik"].sum()
+    for prec in ("fp32", "fp64"):
+        g = ls.loglik_grad(m, rec, prec, grad=True)
+        grg = g["grad_rho"].cpu().numpy()
+        out[f"{prec}_grad_rho_rel_err_vs_oracle"] = float(np.abs(grg - gr).max() / np.abs(gr).max())
+        out[f"{prec}_grad_mu_rel_err_vs_oracle"] = float(abs(g["grad_mu"].item() - gm) / abs(gm))
+        out[f"{prec}_pac_rel_err_vs_oracle"] = float(abs(g["pac"].item() - ll) / abs(ll))
+    out["oracle_sample"] = "256 seeded recipients, exact score (full forward table per recipient)"
+    return out
+
+
+def large_workload(ls, torch, oracle, nthreads, window=12_500, check=64):
+    """All 100,000 recipients of the large workload (L = 10,000, 5 targets)
+    in windows, each writing its rows of the half distances into five
+    resident 100k x 100k FP32 matrices, then the in-place symmetrisation.
+    One timed pass; FP32 posterior and log-likelihood error against the
+    oracle on `check` seeded recipients."""
+    from lsinputs import make_inputs, seeded_recipients
+    t0 = time.time()
+    x = make_inputs("c5")
+    N, L, targets = x["N"], x["L"], x["targets"]
+    T = len(targets)
+    log(f"inputs c5: N={N} L={L} T={T} ({time.time() - t0:.1f}s)")
+    m = ls.Model(x["H"], N, x["rho"], x["mu"])
+    # the window: what fits beside the matrices (its snapshots and two tables
+    # take (T + 2) N FP32 values per recipient), at most `window`
+    free, _ = torch.cuda.mem_get_info()
+    d_bytes = T * N * N * 4
+    fit = int((free - d_bytes - (8 << 30)) // ((T + 2) * N * 4))
+    window = min(window, fit)
+    if window < 256:
+        return {"error": f"not enough device memory for {T} resident {N}x{N} matrices "
+                         f"({free / 2**30:.0f} GiB free)"}
+    D = torch.empty((T, N, N), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with Timer(torch) as t:
+        res = ls.distance_matrices(m, targets, "fp32", window=window, D=D)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = t.ms()
+    cells = float(N) * N * L
+    out = {"workload": f"N={N} haplotypes, L={L} variants, mosaic of {x['cfg']['K']} founders, "
+                       f"T={T} targets, {T} resident {N}x{N} FP32 distance matrices",
+           "value": cells / (ms / 1e3), "unit": "cells/s", "seconds": ms / 1e3,
+           "wall_seconds": wall, "window": window, "shape": list(ls.kernel_shape(N, "fp32"))}
+    # D symmetric with a zero diagonal on sampled entries
+    rng = np.random.default_rng(5)
+    a = torch.as_tensor(rng.integers(0, N, 4096), device="cuda")
+    b = torch.as_tensor(rng.integers(0, N, 4096), device="cuda")
+    out["sym_check"] = bool(torch.equal(D[:, a, b], D[:, b, a]) and
+                           bool((D[:, a, a] == 0).all().item()))
+    ll = res["loglik"].cpu().numpy()
+    del res, D
+    torch.cuda.empty_cache()
+    rec = seeded_recipients(N, check, seed=555)
+    t0 = time.perf_counter()
+    ref = oracle.run_pass(x["H"], N, L, x["rho"], x["mu"], rec, targets, want=("P",),
+                          nthreads=nthreads)
+    out["oracle_seconds"] = time.perf_counter() - t0
+    p = ls.decode(m, targets, "fp32", recipients=rec, want=("P",))["P"].double().cpu().numpy()
+    out["max_posterior_err_vs_oracle"] = float(np.abs(p - ref["P"]).max())
+    out["max_rel_loglik_err_vs_oracle"] = float(np.max(np.abs(ll[rec] - ref["llf"]) /
+                                                       np.abs(ref["llf"])))
+    out["oracle_sample"] = f"{len(rec)} seeded recipients, all donors, all variants"
+    return out
 
 
 def main():
@@ -122,26 +262,29 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--err-recipients", type=int, default=256)
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the all-recipient FP32 vs FP64 comparison")
+    ap.add_argument("--no-gradient", action="store_true", help="skip the gradient workload")
+    ap.add_argument("--no-large", action="store_true", help="skip the large workload")
+    ap.add_argument("--profile", action="store_true",
+                    help="the timed steps only (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--stream-probe", action="store_true",
-                    help="print the HBM rates of plain streaming kernels and exit")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
-        return
-    if args.stream_probe:
-        stream_probe()
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1 "
                                    "(recipient sharding across GPUs is a design note only)"}))
         sys.exit(2)
+    if args.profile:
+        args.no_cpu_baseline = args.no_fp64 = args.no_accuracy = True
+        args.no_gradient = args.no_large = True
 
     import torch
 
     import paper_2212_11403_amd as ls
-    from lsinputs import get_config, make_inputs, seeded_recipients
+    from lsinputs import get_config, make_inputs
 
     cfg = get_config(args.config)
     t0 = time.time()
@@ -196,69 +339,32 @@ def main():
         return dict(wall=wall, ms_per_step=1e3 * wall / steps, bwd_ms=bwd_ms, fwd_ms=fwd_ms,
                     sym_ms=sym_ms, status=status, loglik=ll)
 
-    log(f"fp32 shape {ls.kernel_shape(N, 'fp32')}, fp64 shape {ls.kernel_shape(N, 'fp64')}")
+    shape = ls.kernel_shape(N, "fp32")
+    log(f"fp32 shape {shape}, fp64 shape {ls.kernel_shape(N, 'fp64')}")
     r32 = timed("fp32", args.steps, args.warmup)
     cells = float(N) * N * L
     value = cells / (r32["ms_per_step"] / 1e3)
     log(f"fp32: {r32['ms_per_step']:.1f} ms/step (bwd {r32['bwd_ms']:.1f}, fwd+post "
         f"{r32['fwd_ms']:.1f}, sym {r32['sym_ms']:.1f}) -> {value:.3e} cells/s")
-    r64 = None
-    if not args.no_fp64:
-        r64 = timed("fp64", args.fp64_steps, 0)
-        log(f"fp64: {r64['ms_per_step']:.1f} ms/step (bwd {r64['bwd_ms']:.1f}, fwd+post "
-            f"{r64['fwd_ms']:.1f})")
-
-    # posterior error of the FP32 sweep against FP64 (GPU) and against the
-    # FP64 oracle, on seeded recipients (outside the timed region)
-    rec = seeded_recipients(N, max(args.err_recipients, 1), seed=2212)
-    p32 = None
-    if args.err_recipients > 0:
-        p32 = ls.decode(model, targets, "fp32", recipients=rec, want=("P",))["P"]
-    err = {}
-    if p32 is not None and not args.no_fp64:
-        out64 = ls.decode(model, targets, "fp64", recipients=rec, want=("P",))
-        p64 = out64["P"]
-        err["max_posterior_err_fp32_vs_fp64"] = float((p32.double() - p64).abs().max().item())
-        ll32 = r32["loglik"]
-        ll64 = r64["loglik"]
-        err["max_rel_loglik_err_fp32_vs_fp64"] = float(np.max(np.abs(ll32 - ll64) / np.abs(ll64)))
-        del out64, p64
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        nthreads = oracle.default_threads()
-        # about 10-20 s of oracle work on the host's cores
-        sample = seeded_recipients(N, 3 * nthreads, seed=2212)
-        t0 = time.perf_counter()
-        ref = oracle.run_pass(x["H"], N, L, x["rho"], x["mu"], sample, targets, want=("P",),
-                              nthreads=nthreads)
-        dt_cpu = time.perf_counter() - t0
-        cpu_rate = len(sample) * float(N) * L / dt_cpu
-        cpu = {"value": cpu_rate, "unit": "cells/s", "cores": int(nthreads), "kind": "oracle",
-               "sample": f"{len(sample)} seeded recipients x all {N} donors x all {L} variants, "
-                         f"forward+backward+posteriors at {T} targets, FP64 C, {dt_cpu:.1f} s"}
-        if p32 is not None:
-            p_s = ls.decode(model, targets, "fp32", recipients=sample, want=("P",))["P"]
-            err["max_posterior_err_fp32_vs_oracle"] = float(
-                np.abs(p_s.double().cpu().numpy() - ref["P"]).max())
-            del p_s
-        log(f"oracle: {cpu_rate:.3e} cells/s on {nthreads} threads ({dt_cpu:.1f}s)")
-    del p32
 
     # roofline of the dominant kernel: the backward sweep, launched once per
     # SWEEP_CHUNK variants; per-launch figures are averages over the sweep
-    shape = ls.kernel_shape(N, "fp32")
     launches = -(-(L - 1) // SWEEP_CHUNK)
-    bwd_s = r32["bwd_ms"] / 1e3
-    achieved = OPS_PER_CELL * cells / bwd_s
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                "unit": "TOP/s", "frac": achieved / VALU_PEAK,
+    launch_s = r32["bwd_ms"] / 1e3 / launches
+    cells_launch = cells / launches
+    flops = FLOPS_PER_CELL * cells_launch / launch_s
+    lane_ops = ISSUE_OPS_PER_CELL * cells_launch / launch_s
+    rows_bytes = SWEEP_CHUNK * N / 8.0                 # one bit per donor and variant
+    snap_bytes = T / launches * float(N) * N * 4       # beta snapshots, FP32
+    roofline = {"bound": "alu", "achieved": flops / 1e12, "peak": FP32_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": flops / FP32_PEAK,
                 "traffic": measured_traffic(shape),
                 "kernel": f"sweep_kernel<PrecF32,{shape[0]},1> (backward)",
-                "ops_per_cell": OPS_PER_CELL, "launches_per_sweep": launches,
-                "cells_per_launch": cells / launches,
-                "launch_ms": r32["bwd_ms"] / launches}
+                "flops_per_cell": FLOPS_PER_CELL, "launches_per_sweep": launches,
+                "cells_per_launch": cells_launch, "launch_ms": launch_s * 1e3,
+                "algorithmic_bytes_per_launch": rows_bytes + snap_bytes,
+                "issue": {"achieved_lane_ops_per_s": lane_ops, "peak_lane_ops_per_s": ISSUE_PEAK,
+                          "frac": lane_ops / ISSUE_PEAK, "ops_per_cell": ISSUE_OPS_PER_CELL}}
     line = {
         "metric": "LS fwd+bwd cell updates/s (N^2 L / s), FP32-scaled sweep",
         "value": value,
@@ -277,19 +383,65 @@ def main():
                    "N": N, "L": L, "targets": T, "slots_per_wave": shape[0],
                    "waves_per_recipient": shape[1]},
         "roofline": roofline,
-        "cpu_baseline": cpu,
+        "cpu_baseline": None,
         "fp32_breakdown_ms": {"backward_sweep": r32["bwd_ms"], "forward_sweep_and_posterior":
                               r32["fwd_ms"], "symmetrise": r32["sym_ms"]},
         "nonfinite_status": int(r32["status"]),
     }
-    if r64 is not None:
-        a64 = OPS_PER_CELL * cells / (r64["bwd_ms"] / 1e3)
+
+    r64 = None
+    if not args.no_fp64:
+        r64 = timed("fp64", args.fp64_steps, 0)
+        log(f"fp64: {r64['ms_per_step']:.1f} ms/step (bwd {r64['bwd_ms']:.1f}, fwd+post "
+            f"{r64['fwd_ms']:.1f})")
+        f64_flops = FLOPS_PER_CELL * cells / (r64["bwd_ms"] / 1e3)
         line["fp64"] = {"value": cells / (r64["ms_per_step"] / 1e3), "ms_per_step":
                         r64["ms_per_step"], "backward_sweep_ms": r64["bwd_ms"],
                         "forward_sweep_and_posterior_ms": r64["fwd_ms"],
                         "shape": list(ls.kernel_shape(N, "fp64")),
-                        "backward_alu_frac": a64 / VALU_PEAK_F64}
-    line.update(err)
+                        "backward_flops_frac": f64_flops / FP64_PEAK}
+        ll32, ll64 = r32["loglik"], r64["loglik"]
+        line["max_rel_loglik_err_fp32_vs_fp64"] = float(np.max(np.abs(ll32 - ll64) / np.abs(ll64)))
+    if not args.no_fp64 and not args.no_accuracy:
+        t0 = time.time()
+        e, _ = c2_accuracy_all(ls, torch, model, targets, N)
+        line["max_posterior_err_fp32_vs_fp64"] = e
+        line["accuracy_scope"] = f"all {N} recipients x {T} targets ({N * N * T:.1e} posteriors)"
+        log(f"fp32 vs fp64 over all recipients: {e:.3e} ({time.time() - t0:.1f}s)")
+
+    oracle = None
+    nthreads = 1
+    if not args.no_cpu_baseline or not args.no_gradient or not args.no_large:
+        import oracle
+        nthreads = oracle.default_threads()
+    if not args.no_cpu_baseline:
+        rate, dt_cpu, sample, ref = oracle_rate(oracle, x, nthreads, 3 * nthreads, 2212)
+        rate1, dt1, _, _ = oracle_rate(oracle, x, 1, 2, 2213)
+        line["cpu_baseline"] = {
+            "value": rate, "unit": "cells/s", "cores": int(nthreads), "kind": "oracle",
+            "sample": f"{len(sample)} seeded recipients x all {N} donors x all {L} variants, "
+                      f"forward+backward+posteriors at {T} targets, FP64 C, {dt_cpu:.1f} s",
+            "one_core": {"value": rate1, "cores": 1,
+                         "sample": f"2 seeded recipients, same work, {dt1:.1f} s"}}
+        p_s = ls.decode(model, targets, "fp32", recipients=sample, want=("P",))["P"]
+        line["max_posterior_err_fp32_vs_oracle"] = float(
+            np.abs(p_s.double().cpu().numpy() - ref["P"]).max())
+        del p_s, ref
+        log(f"oracle: {rate:.3e} cells/s on {nthreads} threads ({dt_cpu:.1f}s), "
+            f"{rate1:.3e} on one ({dt1:.1f}s)")
+    del model
+    torch.cuda.empty_cache()
+
+    if not args.no_gradient:
+        t0 = time.time()
+        line["gradient_workload"] = gradient_workload(ls, torch, oracle, nthreads)
+        log(f"gradient workload: {line['gradient_workload']} ({time.time() - t0:.1f}s)")
+        torch.cuda.empty_cache()
+    if not args.no_large:
+        t0 = time.time()
+        line["large_workload"] = large_workload(ls, torch, oracle, nthreads)
+        log(f"large workload: {line['large_workload']} ({time.time() - t0:.1f}s)")
+        torch.cuda.empty_cache()
     print(json.dumps(line), flush=True)
 
 
