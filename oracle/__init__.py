@@ -20,6 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ls_oracle.c")
+_SRC_CLUSTER = os.path.join(_HERE, "ls_cluster.c")
 _LIB = os.path.join(_HERE, "libls_oracle.so")
 _lib = None
 
@@ -28,10 +29,11 @@ EPS = 2.0 ** -52
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (no GPU code)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_CLUSTER))
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + f".{os.getpid()}.tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-               "-shared", "-pthread", "-o", tmp, _SRC, "-lm"]
+               "-shared", "-pthread", "-o", tmp, _SRC, _SRC_CLUSTER, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -64,6 +66,11 @@ def bind(path: str):
     lib.lso_rho_map_grad.argtypes = [P, i32, f64, f64, P, P, P]
     lib.lso_rho_map_grad.restype = None
     lib.lso_version.restype = ctypes.c_char_p
+    if hasattr(lib, "lso_average_linkage"):
+        lib.lso_average_linkage.argtypes = [P, i32, i32, i32, P, P]
+        lib.lso_average_linkage.restype = ctypes.c_int
+        lib.lso_standardise.argtypes = [P, i32, i32, P]
+        lib.lso_standardise.restype = None
     return lib
 
 
@@ -247,3 +254,33 @@ def rho_map_grad(cM, s, gamma, grad_rho, lib=None):
 
 def version() -> str:
     return _load().lso_version().decode()
+
+
+def average_linkage(D, naive: bool = False, lib=None):
+    """Average pairwise linkage of the symmetric distance matrix D (section
+    6; float32 or float64, computed in that precision; D is not modified).
+    Returns (Z [N-1][4] float64: smaller id, larger id, distance, size;
+    order [N] int32: the dendrogram's leaf order). naive: the O(N^3) scan
+    of every pair at every merge instead of the nearest-slot bookkeeping."""
+    lib = lib or _load()
+    D = np.array(D, copy=True, order="C")
+    if D.dtype not in (np.float32, np.float64) or D.ndim != 2 or D.shape[0] != D.shape[1]:
+        raise ValueError("D must be a square float32 or float64 matrix")
+    N = D.shape[0]
+    Z = np.zeros((max(N - 1, 0), 4))
+    order = np.zeros(N, dtype=np.int32)
+    rc = lib.lso_average_linkage(_ptr(D), N, int(D.dtype == np.float64), int(bool(naive)),
+                                 _ptr(Z), _ptr(order))
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    return Z, order
+
+
+def standardise(e, i, lib=None):
+    """Standardised half-distance column of recipient i (section 2.2; zero
+    deviation gives zeros): [N] float64."""
+    lib = lib or _load()
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    z = np.empty_like(e)
+    lib.lso_standardise(_ptr(e), e.size, int(i), _ptr(z))
+    return z
