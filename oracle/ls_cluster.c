@@ -23,7 +23,8 @@
  * clusters in slots a < b puts the merged cluster in slot a and empties
  * slot b. Among the pairs of occupied slots at the smallest distance the
  * merge takes the pair (a, b), a < b, with the smallest a, then the smallest
- * b. Ids follow the usual linkage-matrix convention: leaves 0..N-1, the
+ * b; a NaN distance (a column of a total underflow) comes after every
+ * number. Ids follow the usual linkage-matrix convention: leaves 0..N-1, the
  * cluster made by merge m gets id N + m. Output row m of Z: the smaller id,
  * the larger id, the merge distance, the size of the merged cluster.
  *
@@ -37,6 +38,22 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* The order in which candidate merges are taken: by distance, a NaN
+ * distance after every number; equal distances (or two NaNs) by the slot
+ * pair, smaller first. */
+#define ORDER_DEF(T, SUF)                                                                        \
+    static int before_##SUF(T d1, int32_t p1, int32_t q1, T d2, int32_t p2, int32_t q2)          \
+    {                                                                                            \
+        int n1 = isnan(d1), n2 = isnan(d2);                                                      \
+        if (n1 != n2)                                                                            \
+            return n2;                                                                           \
+        if (!n1 && d1 != d2)                                                                     \
+            return d1 < d2;                                                                      \
+        return p1 < p2 || (p1 == p2 && q1 < q2);                                                 \
+    }
+ORDER_DEF(float, f32)
+ORDER_DEF(double, f64)
 
 #define LINKAGE_DEFS(T, SUF)                                                                     \
     static int linkage_naive_##SUF(T *D, int32_t N, double *Z)                                    \
@@ -65,7 +82,7 @@
                     if (!live[j])                                                                \
                         continue;                                                                \
                     T d = D[(int64_t)i * N + j];                                                 \
-                    if (a < 0 || d < best) {                                                     \
+                    if (a < 0 || before_##SUF(d, i, j, best, a, b)) {                            \
                         best = d;                                                                \
                         a = i;                                                                   \
                         b = j;                                                                   \
@@ -94,7 +111,7 @@
             if (k == i || !live[k])                                                              \
                 continue;                                                                        \
             T d = D[(int64_t)i * N + k];                                                         \
-            if (best < 0 || d < bd) {                                                            \
+            if (best < 0 || before_##SUF(d, k, 0, bd, best, 0)) {                                \
                 best = k;                                                                        \
                 bd = d;                                                                          \
             }                                                                                    \
@@ -134,7 +151,7 @@
                 if (!live[i])                                                                    \
                     continue;                                                                    \
                 int32_t p = i < nn[i] ? i : nn[i], q = i < nn[i] ? nn[i] : i;                    \
-                if (a < 0 || nd[i] < best || (nd[i] == best && (p < a || (p == a && q < b)))) {  \
+                if (a < 0 || before_##SUF(nd[i], p, q, best, a, b)) {                           \
                     best = nd[i];                                                                \
                     a = p;                                                                       \
                     b = q;                                                                       \
@@ -154,7 +171,7 @@
                     nn[k] = nearest_##SUF(D, N, live, k, &nd[k]);                                \
                 } else {                                                                         \
                     T d = D[(int64_t)k * N + a];                                                 \
-                    if (d < nd[k] || (d == nd[k] && a < nn[k])) {                                \
+                    if (before_##SUF(d, a, 0, nd[k], nn[k], 0)) {                                \
                         nn[k] = a;                                                               \
                         nd[k] = d;                                                               \
                     }                                                                            \

@@ -127,6 +127,19 @@ def test_nearest_slot_bookkeeping_equals_full_scan(dtype, maker, N, seed):
     assert np.array_equal(o1, o2)
 
 
+def test_nan_distances_merge_last():
+    """A NaN distance (a recipient column of a total underflow) comes after
+    every number; NaN pairs among themselves by slot."""
+    D = np.array([[0, 1, np.nan, 4], [1, 0, np.nan, 2], [np.nan, np.nan, 0, np.nan],
+                  [4, 2, np.nan, 0]], dtype=np.float64)
+    Z, order = oracle.average_linkage(D)
+    assert Z[0].tolist() == [0, 1, 1, 2]
+    assert Z[1].tolist() == [3, 4, 3, 3]
+    assert Z[2, 0] == 2 and Z[2, 1] == 5 and np.isnan(Z[2, 2]) and Z[2, 3] == 4
+    Zn, _ = oracle.average_linkage(D, naive=True)
+    assert np.array_equal(Z, Zn, equal_nan=True)
+
+
 def test_input_not_modified_and_sizes():
     D = _rand_points(30, 9).astype(np.float32)
     D0 = D.copy()
@@ -177,9 +190,9 @@ def test_standardise_affine_invariance():
 MUTANTS = {
     "unweighted_update": ("T s = t + u;", "T s = D[(int64_t)a * N + k] + D[(int64_t)b * N + k];"),
     "update_wrong_divisor": ("T d = s / n;", "T d = s / (na + nb + 1);"),
-    "naive_tie_takes_last": ("if (a < 0 || d < best) {", "if (a < 0 || d <= best) {"),
-    "nn_tie_takes_larger_slot": ("(nd[i] == best && (p < a || (p == a && q < b)))",
-                                 "(nd[i] == best && (p > a || (p == a && q > b)))"),
+    "tie_takes_larger_slot": ("return p1 < p2 || (p1 == p2 && q1 < q2);",
+                              "return p1 > p2 || (p1 == p2 && q1 > q2);"),
+    "nan_first": ("            return n2;", "            return n1;"),
     "nn_not_rescanned": ("if (nn[k] == a || nn[k] == b) {", "if (nn[k] == b) {"),
     "leaf_order_swapped": ("stack[top++] = (int32_t)z[1]; /* right", "stack[top++] = (int32_t)z[0]; /* right"),
     "standardise_sample_sd": ("double sd = sqrt(v / (double)(N - 1));",
@@ -207,7 +220,8 @@ def _build_mutant(tmp_path, name, find, repl):
 
 def _pins_pass(lib) -> bool:
     tests = [test_hand_worked_example, test_ties_take_the_smallest_slots,
-             test_two_groups_with_ties, test_standardise_matches_numpy,
+             test_two_groups_with_ties, test_nan_distances_merge_last,
+             test_standardise_matches_numpy,
              test_standardise_zero_deviation_gives_zeros]
     saved = oracle._lib
     try:
