@@ -65,11 +65,19 @@ typedef enum {
  * LS_FP32: single-precision vectors with per-step renormalisation; column
  *   sums reduced in FP32 lanes; the log scale factors and the
  *   log-likelihood accumulate in FP64.
- * LS_FP32_F16STORE: as LS_FP32 during a sweep (the vectors stay in FP32
- *   registers); the tables between sweeps hold the vectors in IEEE half
- *   precision, multiplied by a fixed per-direction scale kappa (see ls_table),
- *   which halves their memory. Snapshots, posteriors and distances are FP32.
- *   A precision-study option: each store to a table rounds to half. */
+ * LS_FP32_F16STORE: FP16-stored vectors: FP32 arithmetic as LS_FP32, but
+ *   the vector is rounded to IEEE half precision after every update, at
+ *   every variant, and the tables hold it in half (half their memory). The
+ *   per-recipient scale is the FP64 log scale of the table and a fixed
+ *   factor kappa per direction that keeps entries inside half's range (see
+ *   ls_table); the vectors are renormalised at every step. Snapshots,
+ *   posteriors and distances are FP32. A precision-study option: its error
+ *   against LS_FP64 is that of half storage. Half holds an entry down to
+ *   about 2^-38 of its vector's largest (its smallest subnormal over kappa);
+ *   smaller entries round to 0 and stay 0 until a jump refills them. With a
+ *   prior whose weights span more than that, a donor can hold a large
+ *   posterior as the product of an alpha and a beta entry each below that
+ *   range, and half storage loses it (the tables stay finite). */
 typedef enum { LS_FP64 = 0, LS_FP32 = 1, LS_FP32_F16STORE = 2 } ls_precision;
 
 /* Status word flags (per recipient, device memory). */
@@ -115,20 +123,20 @@ typedef struct {
                              uniform prior 1/(N-1). Used by decoding, the
                              log-likelihood and its gradient, with a scalar
                              mu or mu_vec, in every precision that offers
-                             them. With LS_FP32_F16STORE a backward table
-                             entry is 16384 v_j / sum_k (N-1) Pi_ki v_k,
-                             which can exceed the half range when the
-                             prior gives the copied donors far less than
-                             average weight; a sweep that resumes from such
-                             a table reports LS_FLAG_NONFINITE (use
-                             LS_FP32). The caller
+                             them. With LS_FP32_F16STORE a backward
+                             table with a prior holds a positive multiple
+                             of beta per recipient (W/S beta with W the
+                             prior-weighted and S the plain column sum of
+                             beta theta), which stays inside half's range
+                             for any prior; posteriors do not depend on the
+                             multiple. The caller
                              keeps it alive and unchanged while the model
                              is in use. */
 } ls_model;
 
 /* Device bytes of the workspace ls_model_init lays the internal haplotype
  * rows (about 2 N L / 8 bytes), the per-variant FP32 transition
- * coefficients of the sweeps (32 L bytes), the per-variant emission
+ * coefficients of the sweeps (40 L bytes), the per-variant emission
  * tables for a vector mu (32 L + 8 bytes) and the checks of a prior matrix
  * (16 N bytes) into. */
 size_t ls_model_workspace_bytes(int32_t N, int32_t L);
@@ -151,8 +159,10 @@ ls_status ls_model_init(ls_model *m, void *workspace, size_t ws_bytes, void *str
  * with i = recipients[r]. The diagonal entry j == i is always 0.
  * Element type of state: double (LS_FP64), float (LS_FP32) or IEEE half
  * (LS_FP32_F16STORE). Half tables hold kappa * alpha (kappa = 2^14) or
- * kappa * beta (kappa = 2^14 / (N-1)); the recursions and posteriors do not
- * depend on that factor. */
+ * kappa * beta (kappa = 2^14 / (N-1); with a prior matrix kappa times a
+ * positive multiple of beta, see ls_model.prior), and their log_scale
+ * accounts for the factor; the recursions and posteriors do not depend on
+ * it. */
 typedef struct {
     void *state;               /* device, [R][N] */
     double *log_scale;         /* device, [R] */
@@ -233,6 +243,51 @@ ls_status ls_posterior_distance(const ls_table *fwd, const ls_table *bck, const 
  * equal E (in place). Errors: LS_ERR_ARG, LS_ERR_DEVICE. */
 ls_status ls_distance_symmetrise(const void *E, void *D, int32_t N, int32_t T,
                                  ls_precision prec, void *stream);
+
+/* Average pairwise linkage (Sokal and Michener's method, with which the paper
+ * clusters a distance matrix, section 6) of T symmetric N x N distance
+ * matrices, each by one workgroup, side by side.
+ * Definition: every haplotype starts as its own cluster; the two clusters
+ * at the smallest distance merge, the distance between clusters being the
+ * mean of the pairwise distances of their members, kept with the update
+ * d(A u B, C) = (|A| d(A,C) + |B| d(B,C)) / (|A| + |B|) evaluated in the
+ * matrix's precision (each operation rounded in that order).
+ * Slots and ties: cluster k starts in slot k; merging slots a < b keeps the
+ * merged cluster in slot a. Among the pairs at the smallest distance the
+ * merge takes the smallest slot a, then the smallest b; a NaN distance comes
+ * after every number. The merges are those of the plain algorithm that
+ * scans every pair at every merge, bit for bit.
+ * D: device, [T][N][N], double if prec == LS_FP64 else float, symmetric
+ * (its diagonal is not read); overwritten (the rows and columns of merged
+ * clusters hold the merged distances).
+ * Z: device, [T][N-1][4] double: per merge m, the two cluster ids (leaves
+ * 0..N-1, merge m makes id N + m; smaller id first), the merge distance and
+ * the size of the merged cluster (the usual linkage-matrix layout).
+ * order: device, [T][N] int32, the dendrogram's leaf order (each merge's
+ * smaller id first), or NULL.
+ * workspace: device, >= ls_average_linkage_workspace_bytes(N, T, prec)
+ * bytes (about 21 N T bytes), 256-byte aligned; contents undefined after.
+ * Errors: LS_ERR_ARG, LS_ERR_WORKSPACE, LS_ERR_DEVICE. */
+size_t ls_average_linkage_workspace_bytes(int32_t N, int32_t T, ls_precision prec);
+ls_status ls_average_linkage(void *D, int32_t N, int32_t T, ls_precision prec, double *Z,
+                             int32_t *order, void *workspace, size_t ws_bytes, void *stream);
+
+/* Standardised half-distance rows (section 2.2: a recipient's column of
+ * distances standardised, with 0 where its deviation is 0), in place: row
+ * (k, r) of N half distances at E + k * out_target_stride + r *
+ * out_row_stride (the layout of ls_forward's E; strides 0 = contiguous
+ * [T][R][N]) belongs to recipient i = recipients[r]:
+ *   z_j = (e_j - mean) / sd over the donors j != i, with the mean and the
+ *   population standard deviation (divisor N - 1), accumulated in FP64;
+ *   z_i = 0; a row whose donor entries are all equal (the zero-total case
+ *   of eq. postprob gives every donor -log(eps)/2) becomes 0; a NaN row
+ *   stays NaN.
+ * Symmetrising standardised rows (ls_distance_symmetrise) gives standardised
+ * distances. E: device, double for LS_FP64 else float; recipients: device
+ * [R]. Errors: LS_ERR_ARG, LS_ERR_SHAPE (overlapping rows), LS_ERR_DEVICE. */
+ls_status ls_standardise_rows(void *E, const int32_t *recipients, int32_t R, int32_t T,
+                              int32_t N, int64_t out_target_stride, int64_t out_row_stride,
+                              ls_precision prec, void *stream);
 
 /* Log-likelihood of each recipient, log P(h_i | h_-i) = log F^{L-1}, their
  * sum (the product-of-approximate-conditionals log-likelihood over all

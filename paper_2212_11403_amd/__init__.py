@@ -14,7 +14,8 @@ __all__ = [
     "LS_FP32", "LS_FP32_F16STORE", "LS_FP64", "LS_MAX_TARGETS", "LS_OK", "LS_WARN_NONFINITE",
     "LsError", "load", "Model", "Table", "forward", "backward", "posterior_distance",
     "distance_symmetrise", "loglik_grad", "kernel_shape", "status_check", "decode",
-    "PACLoglik", "RhoMap", "calc_rho", "rho_map_grad", "distance_matrices",
+    "PACLoglik", "RhoMap", "calc_rho", "rho_map_grad", "distance_matrices", "average_linkage",
+    "standardise_rows",
 ]
 
 
@@ -23,7 +24,8 @@ def __getattr__(name):
     # package (e.g. to build it) does not pull in torch
     if name in ("Model", "Table", "forward", "backward", "posterior_distance",
                 "distance_symmetrise", "loglik_grad", "kernel_shape", "status_check", "decode",
-                "io_dtype", "prec_code", "calc_rho", "rho_map_grad", "distance_matrices"):
+                "io_dtype", "prec_code", "calc_rho", "rho_map_grad", "distance_matrices",
+                "average_linkage", "standardise_rows"):
         from . import api
         return getattr(api, name)
     if name in ("PACLoglik", "RhoMap"):

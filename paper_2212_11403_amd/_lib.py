@@ -31,7 +31,8 @@ EXPORTED = [
     "ls_forward", "ls_backward", "ls_posterior_distance", "ls_distance_symmetrise",
     "ls_loglik_grad", "ls_loglik_grad_workspace_bytes", "ls_status_check",
     "ls_kernel_shape", "ls_status_string", "ls_version", "ls_calc_rho", "ls_rho_map_grad",
-    "ls_loglik_checkpoint", "ls_loglik_grad_adjoint",
+    "ls_loglik_checkpoint", "ls_loglik_grad_adjoint", "ls_average_linkage",
+    "ls_average_linkage_workspace_bytes", "ls_standardise_rows",
 ]
 
 
@@ -111,6 +112,9 @@ def load():
         "ls_loglik_grad": (ctypes.c_int, [M, P, I32, ctypes.c_int, P, P, P, P, P, SZ, P]),
         "ls_loglik_grad_workspace_bytes": (SZ, [M, I32, ctypes.c_int]),
         "ls_loglik_checkpoint": (ctypes.c_int, [M, P, I32, ctypes.c_int, P, P, P, SZ, P]),
+        "ls_average_linkage_workspace_bytes": (SZ, [I32, I32, ctypes.c_int]),
+        "ls_average_linkage": (ctypes.c_int, [P, I32, I32, ctypes.c_int, P, P, P, SZ, P]),
+        "ls_standardise_rows": (ctypes.c_int, [P, P, I32, I32, I32, I64, I64, ctypes.c_int, P]),
         "ls_loglik_grad_adjoint": (ctypes.c_int, [M, P, I32, ctypes.c_int, P, P, P, SZ, P]),
         "ls_status_check": (ctypes.c_int, [P, I32, P]),
         "ls_kernel_shape": (ctypes.c_int, [I32, ctypes.c_int, I32, ctypes.POINTER(I32),

@@ -417,3 +417,50 @@ def distance_matrices(model: Model, targets: Sequence[int], prec="fp32", window:
         ll[r0:r1].copy_(fwd.log_scale[:R])
     distance_symmetrise(D, D, pc, stream)
     return dict(D=D, loglik=ll)
+
+
+def average_linkage(D: torch.Tensor, prec=None, order: bool = True, stream=None):
+    """Average pairwise linkage (section 6) of one [N][N] or T [T][N][N]
+    symmetric distance matrices on the device (float32, or float64 for the
+    FP64 path). D is overwritten. Returns (Z [T][N-1][4] float64: smaller
+    id, larger id, merge distance, size; order [T][N] int32 leaf order, or
+    None), with the leading T dropped for a single matrix."""
+    single = D.dim() == 2
+    Dm = D.unsqueeze(0) if single else D
+    if not Dm.is_contiguous() or Dm.shape[-1] != Dm.shape[-2]:
+        raise ValueError("D must be contiguous [T][N][N]")
+    if prec is None:
+        prec = "fp64" if D.dtype == torch.float64 else "fp32"
+    pc = prec_code(prec)
+    if (D.dtype == torch.float64) != (pc == LS_FP64):
+        raise ValueError("D's dtype does not match the precision")
+    T, N = int(Dm.shape[0]), int(Dm.shape[-1])
+    lib = _lib.load()
+    Z = torch.empty((T, max(N - 1, 0), 4), dtype=torch.float64, device=D.device)
+    o = torch.empty((T, N), dtype=torch.int32, device=D.device) if order else None
+    nbytes = lib.ls_average_linkage_workspace_bytes(N, T, pc)
+    ws = torch.empty(int(nbytes), dtype=torch.uint8, device=D.device)
+    check(lib.ls_average_linkage(_p(Dm), N, T, pc, _p(Z) if N > 1 else None, _p(o), _p(ws),
+                                 nbytes, _stream(stream)), "ls_average_linkage")
+    if single:
+        return Z[0], (o[0] if o is not None else None)
+    return Z, o
+
+
+def standardise_rows(E: torch.Tensor, recipients, prec=None, stream=None,
+                     out_strides=(0, 0), N=None) -> torch.Tensor:
+    """Standardise half-distance rows in place (section 2.2): E [T][R][N]
+    (or [R][N]) as ls_forward writes it, row r of recipient recipients[r];
+    with out_strides, rows of N entries (default: E's last dimension) at
+    those element strides from E's start."""
+    if prec is None:
+        prec = "fp64" if E.dtype == torch.float64 else "fp32"
+    rec = recipients.to(E.device, torch.int32).contiguous() if torch.is_tensor(recipients) \
+        else torch.as_tensor(np.asarray(recipients, dtype=np.int32)).to(E.device)
+    R = int(rec.numel())
+    N = int(E.shape[-1]) if N is None else int(N)
+    T = 1 if E.dim() == 2 else int(E.shape[0])
+    check(_lib.load().ls_standardise_rows(_p(E), _p(rec), R, T, N, int(out_strides[0]),
+                                          int(out_strides[1]), prec_code(prec), _stream(stream)),
+          "ls_standardise_rows")
+    return E

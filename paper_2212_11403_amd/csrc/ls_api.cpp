@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "ls.h"
+#include "ls_cluster.h"
 #include "ls_internal.h"
 
 using lsk::Shape;
@@ -166,7 +167,11 @@ ls_status check_model(const ls_model *m) {
     return LS_OK;
 }
 
-void fill_scalars(SweepArgs &a, const ls_model *m, int prec, int dir) {
+// `fold`: the forward multiplies the emission divisor back into c and b, so
+// that its vector is kappa alpha^l (decoding tables); without it the forward
+// keeps the divided pairs' scale and adds the divisor's log per step, as the
+// gradient's forward recursion does (see loglik_grad_impl).
+void fill_scalars(SweepArgs &a, const ls_model *m, int prec, int dir, bool fold = true) {
     const double n1 = (double)(m->N - 1);
     double kappa = 1.0;
     if (prec == LS_FP32_F16STORE) kappa = dir == 0 ? 16384.0 : 16384.0 / n1;
@@ -174,16 +179,22 @@ void fill_scalars(SweepArgs &a, const ls_model *m, int prec, int dir) {
     a.N = m->N;
     a.L = m->L;
     a.NF = m->N / 64;
-    lsk::Emissions em = lsk::sweep_emissions(m->mu, prec != LS_FP64);
-    if (m->mu_vec) em.log_unit = 0.0;  // per variant, from the prefix table
+    lsk::Emissions em = lsk::sweep_emissions(m->mu);
+    if (m->mu_vec) {
+        // per variant: in the coefficient tables (forward) or from the
+        // prefix table (backward); the FP64 pairs are not divided
+        em.log_unit = 0.0;
+        em.unit = 1.0;
+    }
     a.th_match = em.match;
     a.th_mis = em.mis;
     a.kappa = kappa;
     a.inv_kappa = 1.0 / kappa;
     if (dir == 0) {
-        a.cnum = kappa;
-        a.bmul = kappa / n1;
-        a.log_off = em.log_unit - std::log(kappa);
+        const double u = fold ? em.unit : 1.0;
+        a.cnum = kappa * u;
+        a.bmul = kappa / n1 * u;
+        a.log_off = (fold ? 0.0 : em.log_unit) - std::log(kappa);
     } else {
         a.cnum = kappa * n1;
         a.bmul = kappa;
@@ -198,6 +209,15 @@ const float *coef_table(const ls_model *m, int prec, int dir) {
     const int k = (prec == LS_FP32 ? lsk::kCoefF32Fwd : lsk::kCoefF16Fwd) + (dir ? 1 : 0);
     const char *base = reinterpret_cast<const char *>(m->Hr) + coef_offset_bytes(m->N, m->L);
     return reinterpret_cast<const float *>(base) + (size_t)k * 2 * (size_t)m->L;
+}
+
+// The forward coefficients of the gradient's recursion (divided emission
+// pairs' scale), or null for the FP64 sweep.
+const float *grad_forward_coefs(const ls_model *m, int prec) {
+    if (prec == LS_FP64) return nullptr;
+    return reinterpret_cast<const float *>(reinterpret_cast<const char *>(m->Hr) +
+                                           coef_offset_bytes(m->N, m->L)) +
+           (size_t)lsk::kCoefF32FwdGrad * 2 * (size_t)m->L;
 }
 
 // Per-variant mu: the emission pairs in the sweep's arithmetic type and, for
@@ -230,13 +250,15 @@ hipError_t launch_sweep(int prec, int dir, const SweepPtrs &p, const SweepArgs &
 
 // Variants per sweep launch. A long sweep is split into launches of at most
 // this many variants, each resuming from the table the previous one left
-// (resumption is exact in FP64 and FP32). Every launch starts all groups at
+// (resumption is exact in every precision). Every launch starts all groups at
 // the same variant; within one long launch the groups drift apart, the rows
 // they read at any moment spread beyond the L2 cache and the scalar row loads
 // fall through to the last-level cache. Measured backward sweep at N = 10,000,
 // L = 100,000: one launch 1044 ms; chunks of 8192: 984; 4096: 913; 2048: 882;
 // 1024: 883 ms (row fetches beyond L2: 325 GB at 4096, 62 GB at 1024).
-// FP16-stored tables are not split: their stores round to half.
+// FP16-stored sweeps round the vector to half at every step, so a table
+// stored at a launch boundary holds exactly the values the sweep carries on
+// with, and they are split the same way.
 constexpr int32_t kSweepChunk = 2048;
 
 // The chunk length (LS_SWEEP_CHUNK overrides it, for tuning).
@@ -250,7 +272,6 @@ int32_t sweep_chunk() {
 
 hipError_t run_chunks(int prec, int dir, const SweepPtrs &p, const SweepArgs &a, Shape sh,
                       hipStream_t st) {
-    if (prec == LS_FP32_F16STORE) return launch_sweep(prec, dir, p, a, sh, st);
     SweepArgs c = a;
     int32_t l0 = a.l0;
     int next = 0;  // next target, in travel order
@@ -374,16 +395,22 @@ ls_status ls_model_init(ls_model *m, void *workspace, size_t ws_bytes, void *str
     uint64_t *Hr = static_cast<uint64_t *>(workspace);
     hipError_t e = lsk::launch_repack(m->H, m->stride_words, m->N, m->L, Hr, hs, st);
     if (e != hipSuccess) return LS_ERR_DEVICE;
+    // forward tables: kappa and kappa / (N-1), times the emission divisor
+    // (fill_scalars' forward cnum and bmul, with the divisor applied last,
+    // so that a constant per-variant mu gives the scalar model's table)
     lsk::CoefScalars cs;
+    cs.unit = lsk::sweep_emissions(m->mu).unit;
     for (int k = 0; k < lsk::kCoefTables; ++k) {
+        const int dir = k & 1;
         SweepArgs sa;
-        fill_scalars(sa, m, k < 2 ? LS_FP32 : LS_FP32_F16STORE, k & 1);
-        cs.cnum[k] = sa.cnum;
-        cs.bmul[k] = sa.bmul;
+        fill_scalars(sa, m, (k == 2 || k == 3) ? LS_FP32_F16STORE : LS_FP32, dir);
+        cs.cnum[k] = dir ? sa.cnum : sa.kappa;
+        cs.bmul[k] = dir ? sa.bmul : sa.kappa / (double)(m->N - 1);
+        cs.fold[k] = dir == 0 && k != lsk::kCoefF32FwdGrad;
     }
     float *coef = reinterpret_cast<float *>(static_cast<char *>(workspace) +
                                             coef_offset_bytes(m->N, m->L));
-    e = lsk::launch_coef_tables(m->L > 1 ? m->rho : nullptr, m->L, cs, coef, st);
+    e = lsk::launch_coef_tables(m->L > 1 ? m->rho : nullptr, m->mu_vec, m->L, cs, coef, st);
     if (e != hipSuccess) return LS_ERR_DEVICE;
     if (m->mu_vec) {
         char *eb = static_cast<char *>(workspace) + emis_offset_bytes(m->N, m->L);
@@ -445,9 +472,14 @@ ls_status ls_table_copy(ls_table *dst, const ls_table *src, int32_t N, void *str
     return LS_OK;
 }
 
-ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t *targets,
-                     int32_t T, const void *bsnap, void *P, void *E, int64_t out_target_stride,
-                     int64_t out_row_stride, void *stream) {
+namespace {
+
+// ls_forward; with `fold` false (FP32 and FP64 only) the sweep keeps the
+// divided emission pairs' scale, as the gradient's forward does, so that a
+// log-likelihood has the same bits with and without the gradient.
+ls_status forward_impl(ls_table *fwd, const ls_model *m, int32_t t, const int32_t *targets,
+                       int32_t T, const void *bsnap, void *P, void *E, int64_t out_target_stride,
+                       int64_t out_row_stride, void *stream, bool fold) {
     clear_stale_hip_error();
     ls_status s = check_model(m);
     if (s != LS_OK) return s;
@@ -471,7 +503,8 @@ ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t 
     if (!choose_shape(m->N, fwd->prec, &sh, false, m->prior != nullptr)) return LS_ERR_UNSUPPORTED;
     SweepArgs a;
     std::memset(&a, 0, sizeof a);
-    fill_scalars(a, m, fwd->prec, 0);
+    if (fwd->prec == LS_FP32_F16STORE) fold = true;
+    fill_scalars(a, m, fwd->prec, 0, fold);
     a.R = fwd->R;
     a.dir = 0;
     a.l0 = fwd->l;
@@ -489,8 +522,13 @@ ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t 
     SweepPtrs p;
     p.Hr = m->Hr;
     p.rho = m->L > 1 ? m->rho : reinterpret_cast<const double *>(m->Hr);  // only a discarded load when L == 1
-    p.coef = coef_table(m, fwd->prec, 0);
     emission_tables(m, fwd->prec, p);
+    if (fold) {
+        p.coef = coef_table(m, fwd->prec, 0);
+        p.lu_prefix = nullptr;  // the divisors are in the forward coefficient table
+    } else {
+        p.coef = grad_forward_coefs(m, fwd->prec);
+    }
     p.prior = m->prior;
     p.recipients = fwd->recipients;
     p.state = fwd->state;
@@ -508,6 +546,15 @@ ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t 
     fwd->l = t;
     fwd->model_hash = m->hash;
     return LS_OK;
+}
+
+}  // namespace
+
+ls_status ls_forward(ls_table *fwd, const ls_model *m, int32_t t, const int32_t *targets,
+                     int32_t T, const void *bsnap, void *P, void *E, int64_t out_target_stride,
+                     int64_t out_row_stride, void *stream) {
+    return forward_impl(fwd, m, t, targets, T, bsnap, P, E, out_target_stride, out_row_stride,
+                        stream, true);
 }
 
 ls_status ls_backward(ls_table *bck, const ls_model *m, int32_t t, const int32_t *targets,
@@ -586,6 +633,36 @@ ls_status ls_distance_symmetrise(const void *E, void *D, int32_t N, int32_t T,
     return dev(lsk::launch_symmetrise(E, D, N, T, prec == LS_FP64, as_stream(stream)));
 }
 
+size_t ls_average_linkage_workspace_bytes(int32_t N, int32_t T, ls_precision prec) {
+    if (N < 1 || T < 1 || !valid_prec(prec)) return 0;
+    return lsk::linkage_workspace_bytes(N, T, prec == LS_FP64);
+}
+
+ls_status ls_average_linkage(void *D, int32_t N, int32_t T, ls_precision prec, double *Z,
+                             int32_t *order, void *workspace, size_t ws_bytes, void *stream) {
+    clear_stale_hip_error();
+    if (!D || N < 1 || T < 1 || !valid_prec(prec) || (N > 1 && !Z)) return LS_ERR_ARG;
+    if (T > 0x7fffffff / 1024) return LS_ERR_ARG;
+    const size_t need = lsk::linkage_workspace_bytes(N, T, prec == LS_FP64);
+    if (!workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
+        return LS_ERR_WORKSPACE;
+    return dev(lsk::launch_linkage(D, N, T, prec == LS_FP64, Z, order, workspace,
+                                   as_stream(stream)));
+}
+
+ls_status ls_standardise_rows(void *E, const int32_t *recipients, int32_t R, int32_t T,
+                              int32_t N, int64_t out_target_stride, int64_t out_row_stride,
+                              ls_precision prec, void *stream) {
+    clear_stale_hip_error();
+    if (!E || !recipients || R < 1 || T < 1 || T > LS_MAX_TARGETS || N < 2 || !valid_prec(prec))
+        return LS_ERR_ARG;
+    const int64_t rs = out_row_stride ? out_row_stride : (int64_t)N;
+    const int64_t ts = out_target_stride ? out_target_stride : (int64_t)R * rs;
+    if (rs < N || (T > 1 && ts < (int64_t)(R - 1) * rs + N) || ts < 0) return LS_ERR_SHAPE;
+    return dev(lsk::launch_standardise(E, recipients, R, T, N, ts, rs, prec == LS_FP64,
+                                       as_stream(stream)));
+}
+
 ls_status ls_calc_rho(const double *cM, int32_t n, double s, double gamma, double *rho,
                       void *stream) {
     clear_stale_hip_error();
@@ -653,7 +730,8 @@ ls_status loglik_grad_impl(const ls_model *m, const int32_t *recipients, int32_t
                           reinterpret_cast<double *>(ws + lay.off_ll),
                           reinterpret_cast<uint32_t *>(ws + lay.off_status), rec, R, stream);
         if (s != LS_OK) return s;
-        s = ls_forward(&tab, m, m->L - 1, nullptr, 0, nullptr, nullptr, nullptr, 0, 0, stream);
+        s = forward_impl(&tab, m, m->L - 1, nullptr, 0, nullptr, nullptr, nullptr, 0, 0, stream,
+                         false);
         if (s != LS_OK) return s;
         return dev(lsk::launch_loglik_sum(reinterpret_cast<const double *>(ws + lay.off_ll), R,
                                           loglik, pac, st));
@@ -662,7 +740,7 @@ ls_status loglik_grad_impl(const ls_model *m, const int32_t *recipients, int32_t
     std::memset(&ga, 0, sizeof ga);
     ga.Hr = m->Hr;
     ga.rho = m->L > 1 ? m->rho : reinterpret_cast<const double *>(m->Hr);
-    ga.coef_fwd32 = coef_table(m, LS_FP32, 0);
+    ga.coef_fwd32 = grad_forward_coefs(m, LS_FP32);
     ga.coef_bwd32 = coef_table(m, LS_FP32, 1);
     ga.recipients = rec;
     ga.hr_stride = m->hr_stride;

@@ -323,4 +323,122 @@ __device__ __forceinline__ int opaque(int x) {
     return x;
 }
 
+// ---------------------------------------------------------------------------
+// Emission by lane mask. With the emission pair divided by its larger member
+// (see sweep_emissions), one of the two values is exactly 1, so only the
+// lanes whose donor takes the other value r need a multiply. The scalar unit
+// sets EXEC to those lanes (the 64-bit row word XOR `flip`, which is all ones
+// or all zeros), one vector multiply scales them, and EXEC is restored at the
+// end of the block: one vector instruction per 64 cells where a select and a
+// multiply would take two. Multiplying by 1 is exact, so the results are the
+// bits the select form gives. Each block saves and restores EXEC (all lanes
+// are active in the sweep); with NOP it ends with the wait states a DPP
+// instruction needs after a scalar write of EXEC (the last block before a
+// reduction). The scalar XOR also writes SCC, which the blocks declare as
+// clobbered: the compiler keeps the carry of a 64-bit address addition in
+// SCC between its two halves and may place such a pair around a block.
+#define LS_XM(op, i) \
+    "s_xor_b64 exec, %[m" #i "], %[fl]\n\t" op " %[v" #i "], %[r], %[v" #i "]\n\t"
+#define LS_XM8(op) \
+    LS_XM(op, 0) LS_XM(op, 1) LS_XM(op, 2) LS_XM(op, 3) LS_XM(op, 4) LS_XM(op, 5) LS_XM(op, 6) \
+        LS_XM(op, 7)
+#define LS_XM4(op) LS_XM(op, 0) LS_XM(op, 1) LS_XM(op, 2) LS_XM(op, 3)
+#define LS_XM1(op) LS_XM(op, 0)
+#define LS_XM_OUT8                                                                        \
+    [v0] "+v"(v[0]), [v1] "+v"(v[1]), [v2] "+v"(v[2]), [v3] "+v"(v[3]), [v4] "+v"(v[4]), \
+        [v5] "+v"(v[5]), [v6] "+v"(v[6]), [v7] "+v"(v[7]), [sv] "=&s"(sv)
+#define LS_XM_IN8                                                                          \
+    [m0] "s"(m[0]), [m1] "s"(m[1]), [m2] "s"(m[2]), [m3] "s"(m[3]), [m4] "s"(m[4]),       \
+        [m5] "s"(m[5]), [m6] "s"(m[6]), [m7] "s"(m[7]), [fl] "s"(fl), [r] "v"(r)
+#define LS_XM_OUT4 [v0] "+v"(v[0]), [v1] "+v"(v[1]), [v2] "+v"(v[2]), [v3] "+v"(v[3]), [sv] "=&s"(sv)
+#define LS_XM_IN4 \
+    [m0] "s"(m[0]), [m1] "s"(m[1]), [m2] "s"(m[2]), [m3] "s"(m[3]), [fl] "s"(fl), [r] "v"(r)
+#define LS_XM_DEFINE(T, op)                                                                      \
+    template <bool NOP>                                                                          \
+    __device__ __forceinline__ void masked_scale8(T (&v)[8], const uint64_t (&m)[8], uint64_t fl, \
+                                                  T r) {                                         \
+        uint64_t sv;                                                                             \
+        if constexpr (NOP)                                                                       \
+            asm("s_mov_b64 %[sv], exec\n\t" LS_XM8(op) "s_mov_b64 exec, %[sv]\n\ts_nop 4"          \
+                : LS_XM_OUT8 : LS_XM_IN8 : "scc");                                               \
+        else                                                                                     \
+            asm("s_mov_b64 %[sv], exec\n\t" LS_XM8(op) "s_mov_b64 exec, %[sv]"                    \
+                : LS_XM_OUT8 : LS_XM_IN8 : "scc");                                               \
+    }                                                                                            \
+    template <bool NOP>                                                                          \
+    __device__ __forceinline__ void masked_scale4(T (&v)[4], const uint64_t (&m)[4], uint64_t fl, \
+                                                  T r) {                                         \
+        uint64_t sv;                                                                             \
+        if constexpr (NOP)                                                                       \
+            asm("s_mov_b64 %[sv], exec\n\t" LS_XM4(op) "s_mov_b64 exec, %[sv]\n\ts_nop 4"          \
+                : LS_XM_OUT4 : LS_XM_IN4 : "scc");                                               \
+        else                                                                                     \
+            asm("s_mov_b64 %[sv], exec\n\t" LS_XM4(op) "s_mov_b64 exec, %[sv]"                    \
+                : LS_XM_OUT4 : LS_XM_IN4 : "scc");                                               \
+    }                                                                                            \
+    template <bool NOP>                                                                          \
+    __device__ __forceinline__ void masked_scale1(T &v0, uint64_t m0, uint64_t fl, T r) {        \
+        uint64_t sv;                                                                             \
+        if constexpr (NOP)                                                                       \
+            asm("s_mov_b64 %[sv], exec\n\t" LS_XM1(op) "s_mov_b64 exec, %[sv]\n\ts_nop 4"          \
+                : [v0] "+v"(v0), [sv] "=&s"(sv)                                                  \
+                : [m0] "s"(m0), [fl] "s"(fl), [r] "v"(r)                                         \
+                : "scc");                                                                        \
+        else                                                                                     \
+            asm("s_mov_b64 %[sv], exec\n\t" LS_XM1(op) "s_mov_b64 exec, %[sv]"                    \
+                : [v0] "+v"(v0), [sv] "=&s"(sv)                                                  \
+                : [m0] "s"(m0), [fl] "s"(fl), [r] "v"(r)                                         \
+                : "scc");                                                                        \
+    }
+LS_XM_DEFINE(float, "v_mul_f32")
+LS_XM_DEFINE(double, "v_mul_f64")
+#undef LS_XM_DEFINE
+#undef LS_XM_OUT8
+#undef LS_XM_IN8
+#undef LS_XM_OUT4
+#undef LS_XM_IN4
+#undef LS_XM1
+#undef LS_XM4
+#undef LS_XM8
+#undef LS_XM
+
+// v[s] <- r v[s] on the lanes of (mask(s) ^ flip), s < NS, in blocks of
+// 8, 4 and 1 slots; the last block carries the DPP wait states.
+template <int NS, class T, class MaskFn>
+__device__ __forceinline__ void masked_scale_all(T (&v)[NS], MaskFn mask, uint64_t flip, T r) {
+    constexpr int N8 = NS / 8, N4 = (NS % 8) / 4, N1 = NS % 4;
+#pragma unroll
+    for (int q = 0; q < N8; ++q) {
+        T x[8];
+        uint64_t m[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            x[k] = v[8 * q + k];
+            m[k] = mask(8 * q + k);
+        }
+        if (q == N8 - 1 && N4 == 0 && N1 == 0) masked_scale8<true>(x, m, flip, r);
+        else masked_scale8<false>(x, m, flip, r);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[8 * q + k] = x[k];
+    }
+    if constexpr (N4 > 0) {
+        T x[4];
+        uint64_t m[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            x[k] = v[8 * N8 + k];
+            m[k] = mask(8 * N8 + k);
+        }
+        if constexpr (N1 == 0) masked_scale4<true>(x, m, flip, r);
+        else masked_scale4<false>(x, m, flip, r);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[8 * N8 + k] = x[k];
+    }
+#pragma unroll
+    for (int s = NS - N1; s < NS; ++s) {
+        if (s == NS - 1) masked_scale1<true>(v[s], mask(s), flip, r);
+        else masked_scale1<false>(v[s], mask(s), flip, r);
+    }
+}
+
 }  // namespace lsk

@@ -127,7 +127,7 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
     char *ws = ga.ws;
     const int64_t RN = (int64_t)ga.R * ga.N;
     const size_t es = prec == 0 ? 8 : 4;
-    Emissions em = sweep_emissions(ga.mu, prec != 0);
+    Emissions em = sweep_emissions(ga.mu);
     if (ga.emis) em.log_unit = 0.0;  // per variant, from the prefix table
     auto sweep = [&](int dir, int l0, int t, const int32_t *tl, int nt, void *state, void *snap,
                      double *lsc, bool every = false) -> hipError_t {

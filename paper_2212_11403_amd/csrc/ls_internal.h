@@ -50,7 +50,7 @@ struct SweepArgs {
     double inv_kappa;
     double cnum;          // forward: kappa; backward: kappa * (N-1)
     double bmul;          // forward: kappa / (N-1); backward: kappa
-    double log_off;       // per-step log offset: fwd -log(kappa), bwd -log((N-1) kappa),
+    double log_off;       // per-step log offset: fwd -log(kappa), bwd -log((N-1) kappa)
                           // plus the emission unit's log (see sweep_emissions)
     int64_t c_off;        // keep-alpha mode (gradient recompute): element offset, from
                           // the snapshot array, of the [t - l0][R] c of each step
@@ -61,21 +61,22 @@ struct SweepArgs {
 };
 
 // The emission pair a sweep multiplies by, from the form (1-H)(1-2mu)+mu of
-// appendix A.3 evaluated in FP64. The FP64 sweep uses the emissions as they
-// are. Sweeps in FP32 arithmetic use both divided by the larger one (the
-// match value 1-mu for every mu <= 1/2): that factor is then exactly 1 and
-// adds no rounding to most cells, where the rounded 1-mu would bias every
-// step's sum the same way (a log-likelihood error growing with L). Dividing
-// every step's emissions by one constant only rescales the vectors, so its
-// log (`log_unit`) is added to the per-step log offset in FP64.
+// appendix A.3 evaluated in FP64, divided by its larger member `unit` (the
+// match value 1-mu for every mu <= 1/2): that member is then exactly 1, so
+// the emission is a multiply of the other donors only (masked_scale_all) and
+// adds no rounding to most cells; in FP32 the rounded 1-mu would also bias
+// every step's sum the same way (a log-likelihood error growing with L).
+// Dividing every step's emissions by one constant only rescales the
+// vectors. The backward adds its log (`log_unit`) to the per-step log offset
+// in FP64; the forward multiplies it back into the step's coefficients c
+// and b instead, so that its vector is alpha^l itself (see fill_scalars).
 struct Emissions {
-    double match, mis, log_unit;
+    double match, mis, log_unit, unit;
 };
-inline Emissions sweep_emissions(double mu, bool fp32_arith) {
+inline Emissions sweep_emissions(double mu) {
     const double omu = (1.0 - 2.0 * mu) + mu;
-    if (!fp32_arith) return Emissions{omu, mu, 0.0};
-    if (omu >= mu) return Emissions{1.0, mu / omu, std::log(omu)};
-    return Emissions{omu / mu, 1.0, std::log(mu)};
+    if (omu >= mu) return Emissions{1.0, mu / omu, std::log(omu), omu};
+    return Emissions{omu / mu, 1.0, std::log(mu), mu};
 }
 
 // Kernel shape: 64-donor register slots per wave, waves per recipient.
@@ -182,17 +183,29 @@ __host__ __device__ constexpr int special_slots(int nslot) { return nslot < 4 ? 
 // c = A_l / S and b = B_l in the sweep's update v <- theta (c v + b):
 //   forward:  l = 0: (0, bmul); l >= 1: ((1 - rho_{l-1}) cnum, rho_{l-1} bmul)
 //   backward: l <= L-2: ((1 - rho_l) cnum, rho_l bmul); l = L-1: (0, 0), unused
-// Each product is formed in FP64 and rounded once to FP32, which is what the
-// sweep computed per variant before, so results do not change.
-enum { kCoefF32Fwd = 0, kCoefF32Bwd = 1, kCoefF16Fwd = 2, kCoefF16Bwd = 3, kCoefTables = 4 };
+// Each product is formed in FP64 and rounded once to FP32. The forward
+// tables of the decoding sweeps (`fold`) multiply both by the emission
+// divisor (sweep_emissions: `unit`, or with a per-variant mu that of variant
+// l) last; the gradient's forward recursion keeps the divided pairs' scale
+// (kCoefF32FwdGrad) and adds the divisors' logs instead.
+enum {
+    kCoefF32Fwd = 0,
+    kCoefF32Bwd = 1,
+    kCoefF16Fwd = 2,
+    kCoefF16Bwd = 3,
+    kCoefF32FwdGrad = 4,
+    kCoefTables = 5
+};
 struct CoefScalars {
     double cnum[kCoefTables];
     double bmul[kCoefTables];
+    int fold[kCoefTables];
+    double unit;
 };
 
 // Miscellaneous kernels (ls_misc.hip).
-hipError_t launch_coef_tables(const double *rho, int32_t L, const CoefScalars &cs, float *out,
-                              hipStream_t st);
+hipError_t launch_coef_tables(const double *rho, const double *mu_vec, int32_t L,
+                              const CoefScalars &cs, float *out, hipStream_t st);
 hipError_t launch_repack(const uint32_t *H, int64_t stride_words, int32_t N, int32_t L,
                          uint64_t *Hr, int64_t hr_stride, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);

@@ -47,11 +47,18 @@ hipError_t launch_repack(const uint32_t *H, int64_t stride_words, int32_t N, int
 
 // One thread per variant writes its pair in all coefficient tables.
 __global__ void __launch_bounds__(256)
-coef_tables_kernel(const double *__restrict__ rho, int32_t L, CoefScalars cs,
-                   float *__restrict__ out) {
+coef_tables_kernel(const double *__restrict__ rho, const double *__restrict__ mu_vec, int32_t L,
+                   CoefScalars cs, float *__restrict__ out) {
 #pragma clang fp contract(off)
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= L) return;
+    // the divisor of this variant's emission pair (as in sweep_emissions)
+    double unit = cs.unit;
+    if (mu_vec) {
+        const double mu = mu_vec[l];
+        const double omu = (1.0 - 2.0 * mu) + mu;
+        unit = omu >= mu ? omu : mu;
+    }
 #pragma unroll
     for (int k = 0; k < kCoefTables; ++k) {
         double A = 0.0, B = 0.0;
@@ -63,6 +70,10 @@ coef_tables_kernel(const double *__restrict__ rho, int32_t L, CoefScalars cs,
                 A = (1.0 - rr) * cs.cnum[k];
                 B = rr * cs.bmul[k];
             }
+            if (cs.fold[k]) {
+                A *= unit;
+                B *= unit;
+            }
         } else if (l <= L - 2) {  // backward: variant l uses rho_l
             const double rr = rho[l];
             A = (1.0 - rr) * cs.cnum[k];
@@ -73,11 +84,11 @@ coef_tables_kernel(const double *__restrict__ rho, int32_t L, CoefScalars cs,
     }
 }
 
-hipError_t launch_coef_tables(const double *rho, int32_t L, const CoefScalars &cs, float *out,
-                              hipStream_t st) {
+hipError_t launch_coef_tables(const double *rho, const double *mu_vec, int32_t L,
+                              const CoefScalars &cs, float *out, hipStream_t st) {
     if (L < 1) return hipSuccess;
     hipLaunchKernelGGL(coef_tables_kernel, dim3((unsigned)((L + 255) / 256)), dim3(256), 0, st,
-                       rho, L, cs, out);
+                       rho, mu_vec, L, cs, out);
     return hipGetLastError();
 }
 

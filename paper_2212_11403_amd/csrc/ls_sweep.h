@@ -6,8 +6,10 @@
 // Both directions run the same update on a resident vector v:
 //   v <- theta^l (.) (c v + b),  c = num / sum(v_prev),  b = rho-term,
 // where (.) is the elementwise product and theta^l_j is 1-mu on a match of
-// donor j with the recipient at variant l and mu on a mismatch (in FP32
-// arithmetic: 1 and mu/(1-mu), with log(1-mu) per step in the log offset).
+// donor j with the recipient at variant l and mu on a mismatch, both divided
+// by the larger (for mu <= 1/2: 1 and mu/(1-mu), with log(1-mu) per step in
+// the log offset), so the emission scales only the donors whose value is
+// not 1 (a lane-masked multiply).
 //   forward:  v = kappa alpha^l,          c = (1-rho_{l-1}) kappa / S,
 //             b = kappa rho_{l-1} / (N-1); log F^l = log F^{l-1} + log(S_l / kappa)
 //   backward: v = kappa beta^l theta^l,   c = (1-rho_l) kappa (N-1) / S,
@@ -83,6 +85,12 @@ __device__ __forceinline__ SpecSlot special_slot(int q, int NF, int N, int g, bo
 // with y = theta^{l+1} (.) beta^{l+1}, beta^l is proportional to
 // (1 - rho_l) y / W + rho_l, W = sum_j Pi_ji y_j, so c = (1 - rho) kappa
 // (N-1) / W' and log G^l = log G^{l+1} + log(W' / ((N-1) kappa)).
+// With FP16-stored vectors the backward normalises by the plain sum S
+// instead: it keeps (W/S) beta^l, a positive multiple of beta^l per
+// recipient and step, with c = (1 - rho) kappa (N-1) / S and
+// b = kappa rho W' / ((N-1) S), whose entries stay below kappa (N-1) for
+// any prior; its log scale adds log(S / ((N-1) kappa)) per step, which keeps
+// the stored vector times exp(log scale) equal to kappa' beta^l G^l.
 template <class PT, int NSLOT, int DIR, bool EVERY = false, bool MUV = false, bool PI = false>
 __global__ void __launch_bounds__(64 * max_waves_for(NSLOT, sweep_slot_vgprs(PT::vgpr_per_slot, PI)))
 __attribute__((amdgpu_waves_per_eu(
@@ -104,6 +112,16 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
     constexpr int K = special_slots(NSLOT);
     constexpr int NR = NSLOT - K;
     constexpr int MAXW = max_waves_for(NSLOT, sweep_slot_vgprs(PT::vgpr_per_slot, PI));
+    // emission as a lane-masked multiply (every sweep whose emission pairs
+    // have a member equal to 1: all but FP64 with a per-variant mu)
+    constexpr bool XMUL = !(MUV && sizeof(T) == 8);
+    // FP16-stored vectors: rounded to half after every update
+    constexpr bool QH = std::is_same<ST, _Float16>::value;
+    // the FP16-stored backward with a prior matrix normalises by the plain
+    // column sum S and carries W'/S in the rho-term (entries stay below
+    // kappa, inside half's range, whatever the prior)
+    constexpr bool SNORM = QH && PI && DIR == 1;
+    static_assert(!QH || XMUL, "FP16-stored sweeps use the masked emission");
     __shared__ T red[2 * kRedStride];
 
     const int nwaves = uniform(blockDim.x >> 6);
@@ -176,6 +194,19 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
     double base = 0.0;  // log scale the table started from
     int kt = 0;         // next target, in travel order
     T S;                // sum of the resident vector
+    T part_w = (T)0;    // SNORM: this lane's pi'-weighted partial sum
+    T Wsum = (T)0;      // SNORM: the pi'-weighted column sum W'
+    // the workgroup sum of a step's partials (with SNORM also W')
+    auto reduce = [&](T part) __attribute__((always_inline)) -> T {
+        if constexpr (SNORM) {
+            T x[4] = {part, part_w, (T)0, (T)0};
+            block_sum4<MAXW>(x, red, parity, wave);
+            Wsum = x[1];
+            return x[0];
+        } else {
+            return block_sum<MAXW>(part, red, parity, wave, nwaves);
+        }
+    };
 
     // the recipient's own word of variant row l (read one step ahead)
     auto self_word = [&](int l) __attribute__((always_inline)) -> uint64_t {
@@ -216,29 +247,94 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
         else acc0 += x;
     };
     // the column sum a step hands on: the backward with a prior matrix sums
-    // pi' v (its normaliser W'), every other sweep v itself
+    // pi' v (its normaliser W'), every other sweep v itself; the FP16-stored
+    // backward with a prior matrix sums both (SNORM: plain sum in acc0/acc1,
+    // the weighted one in aw0/aw1)
+    T aw0 = (T)0, aw1 = (T)0;
+    auto weighted = [&](int s, T x, T &acc0, T &acc1) __attribute__((always_inline)) {
+        if (s == 0) acc0 = pv[0] * x;
+        else if (s == 1) acc1 = pv[1] * x;
+        else if (s & 1) acc1 = fma(pv[s], x, acc1);
+        else acc0 = fma(pv[s], x, acc0);
+    };
     auto account_sum = [&](int s, T x, T &acc0, T &acc1) __attribute__((always_inline)) {
-        if constexpr (PI && DIR == 1) {
-            if (s == 0) acc0 = pv[0] * x;
-            else if (s == 1) acc1 = pv[1] * x;
-            else if (s & 1) acc1 = fma(pv[s], x, acc1);
-            else acc0 = fma(pv[s], x, acc0);
+        if constexpr (SNORM) {
+            accumulate(s, x, acc0, acc1);
+            weighted(s, x, aw0, aw1);
+        } else if constexpr (PI && DIR == 1) {
+            weighted(s, x, acc0, acc1);
         } else {
             accumulate(s, x, acc0, acc1);
+        }
+    };
+    // FP16 storage: each new vector is rounded to half at every step, so the
+    // sweep carries exactly the values a half table holds
+    auto quantise = [&]() __attribute__((always_inline)) {
+        if constexpr (QH) {
+#pragma unroll
+            for (int s = 0; s < NSLOT; ++s) v[s] = (T)(ST)v[s];
         }
     };
     // Row words of slot s at variant row `row`.
     auto mask_of = [&](const uint64_t *row, int s) __attribute__((always_inline)) -> uint64_t {
         return (s < NR) ? row[reg_base + s] : row[spec_off[s - NR]];
     };
+    // The emission as a lane-masked multiply (masked_scale4): one member of
+    // the pair is exactly 1 (the pair divided by its larger member), so only
+    // the donors taking the other value r are scaled. They are the lanes of
+    // the row word XOR `flip`: the mismatching donors when r is the mismatch
+    // value, the matching ones when it is the match value. Not for the FP64
+    // sweep with a per-variant mu, whose pairs are kept as they are.
+    auto xmul_params = [&](uint64_t sw_bits, T em, T ex, T &r, uint64_t &flip)
+                           __attribute__((always_inline)) {
+        const bool rb = (sw_bits & self_bit) != 0;
+        T m1, x1;
+        if constexpr (MUV) {
+            m1 = em;
+            x1 = ex;
+        } else {
+            m1 = th_m;
+            x1 = th_x;
+        }
+        const bool on_match = m1 != (T)1;
+        r = in_vgpr(on_match ? m1 : x1);
+        // a float compare runs on the vector unit; the flag goes back to a
+        // scalar register, which the EXEC arithmetic needs
+        flip = uniform((int)(rb != on_match)) ? ~0ull : 0ull;
+    };
+    auto xmul_all = [&](const uint64_t *row, uint64_t flip, T r) __attribute__((always_inline)) {
+        masked_scale_all<NSLOT>(
+            v, [&](int s) __attribute__((always_inline)) { return mask_of(row, s); }, flip, r);
+    };
     // v <- theta^l (.) (c v + b); returns this lane's partial sum
     auto step = [&](int l, uint64_t sw_bits, T em, T ex, T c, T b_s)
                     __attribute__((always_inline)) -> T {
         const uint64_t *row = Hr + (int64_t)l * a.hr_stride;
-        T ta, tb;
-        thetas(sw_bits, em, ex, ta, tb);
         const T b = in_vgpr(b_s);
         T acc0, acc1 = (T)0;
+        if constexpr (XMUL) {
+            T r;
+            uint64_t flip;
+            xmul_params(sw_bits, em, ex, r, flip);
+#pragma unroll
+            for (int s = 0; s < NSLOT; ++s) {
+                T bb;
+                if constexpr (PI && DIR == 0) bb = b * pv[s];
+                else bb = (s < NR) ? (s == 0 ? b * keep0 : b) : b * spec_keep[s - NR];
+                v[s] = fma(c, (T)v[s], bb);
+            }
+            // FP16 storage rounds what a table holds: the backward vector
+            // kappa beta^l before its emission, the forward kappa alpha^l
+            if constexpr (DIR == 1) quantise();
+            xmul_all(row, flip, r);
+            if constexpr (DIR == 0) quantise();
+#pragma unroll
+            for (int s = 0; s < NSLOT; ++s) account_sum(s, v[s], acc0, acc1);
+            if constexpr (SNORM) part_w = aw0 + aw1;
+            return acc0 + acc1;
+        }
+        T ta, tb;
+        thetas(sw_bits, em, ex, ta, tb);
 #pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
             const T th = lane_bit(mask_of(row, s)) ? tb : ta;
@@ -259,14 +355,25 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
             const T bb = (s < NR) ? (s == 0 ? b0 : b) : b * spec_keep[s - NR];
             v[s] = fma(c, v[s], bb);
         }
+        quantise();
     };
     // v <- theta^l (.) v; returns this lane's partial sum
     auto emit = [&](int l) __attribute__((always_inline)) -> T {
         const uint64_t *row = Hr + (int64_t)l * a.hr_stride;
         T em, ex, ta, tb;
         emis_at(l, em, ex);
-        thetas(row[self_off], em, ex, ta, tb);
         T acc0, acc1 = (T)0;
+        if constexpr (XMUL) {
+            T r;
+            uint64_t flip;
+            xmul_params(row[self_off], em, ex, r, flip);
+            xmul_all(row, flip, r);
+#pragma unroll
+            for (int s = 0; s < NSLOT; ++s) account_sum(s, v[s], acc0, acc1);
+            if constexpr (SNORM) part_w = aw0 + aw1;
+            return acc0 + acc1;
+        }
+        thetas(row[self_off], em, ex, ta, tb);
 #pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
             const T th = lane_bit(mask_of(row, s)) ? tb : ta;
@@ -352,7 +459,8 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
     // them from the model's coefficient table (formed in FP64, rounded once);
     // the FP64 sweep forms them here. Forward variant l uses rho_{l-1} (and
     // at l = 0 gives c = 0, b = kappa / (N-1), i.e. alpha^0); backward
-    // variant l uses rho_l.
+    // variant l uses rho_l. A decoding forward sweep has the emission
+    // divisor in A and B (cnum, bmul), so its vector is kappa alpha^l.
     auto coefs_at = [&](int l, T &A, T &B) __attribute__((always_inline)) {
         if constexpr (sizeof(T) == 4) {
             A = coef[2 * l];
@@ -515,7 +623,7 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
         if (kt < a.nt && a.tgt_l[kt] == lstart) snapshot();
         if (a.t < lstart) {
             T part = emit(lstart);
-            S = block_sum<MAXW>(part, red, parity, wave, nwaves);
+            S = reduce(part);
             int l = lstart - 1;
             for (;;) {
                 const int lend = kt < a.nt ? a.tgt_l[kt] : a.t;
@@ -533,22 +641,22 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
                     emis_at(ln, em_nx, ex_nx);
                     w_nx = self_word(ln);
                     const T c = coef_c(A, S);
-                    const T b = B;
+                    const T b = SNORM ? coef_c(B * Wsum, S) : B;
                     account(S);
                     part = step(l, wb, em, ex, c, b);
-                    S = block_sum<MAXW>(part, red, parity, wave, nwaves);
+                    S = reduce(part);
                 }
                 // l == lend: a target or the stopping variant; keep beta^l
                 T A, B;
                 coefs_at(l, A, B);
                 const T c = coef_c(A, S);
-                const T b = B;
+                const T b = SNORM ? coef_c(B * Wsum, S) : B;
                 account(S);
                 affine(c, b);
                 if (kt < a.nt && a.tgt_l[kt] == l) snapshot();
                 if (l <= a.t) break;
                 part = emit(l);
-                S = block_sum<MAXW>(part, red, parity, wave, nwaves);
+                S = reduce(part);
                 --l;
             }
         }
@@ -561,9 +669,11 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
         if constexpr (MUV && sizeof(T) == 4) {
             // logs of the divisors of the emission pairs applied here: the
             // forward applies variants first .. t, the backward lstart .. t+1
+            // (a decoding forward sweep has them in its coefficients and
+            // passes no prefix table)
             if constexpr (DIR == 0) {
                 const int first = a.l0 < 0 ? 0 : a.l0 + 1;
-                if (a.t >= first) ls += lu_prefix[a.t + 1] - lu_prefix[first];
+                if (lu_prefix && a.t >= first) ls += lu_prefix[a.t + 1] - lu_prefix[first];
             } else {
                 const int lstart = a.l0 < 0 ? a.L - 1 : a.l0;
                 if (a.t < lstart) ls += lu_prefix[lstart + 1] - lu_prefix[a.t + 1];

@@ -22,6 +22,20 @@ F32_POST_ATOL = 1e-5
 # 3e-7 at L = 10,000 to 100,000; a biased reciprocal or a rounded 1-mu gives
 # 2e-6 to 6e-6 there.
 F32_LOGLIK_RTOL = 1e-6
+# FP16-stored vectors (rounded to half, unit roundoff u = 2^-11, after
+# every update): an entry's relative error settles near u / sqrt(rho) per
+# the renormalised recursion, a few 1e-3 to 1e-2 at the workloads' rho;
+# the bound on posteriors is set from the arithmetic, the measured
+# maximum is printed by each test. The log-likelihood adds the log of each
+# step's column sum of rounded entries: a relative error of at most u per
+# step (all of the mass on one donor), with no common sign, so a random
+# walk of standard deviation up to u sqrt(L / 3), about 0.01 at L = 2,000
+# (an emulation of the half-stored forward on the CPU gives the same
+# figures). Against |log P|, which grows like L, that is 1e-4 to 4e-4 on
+# the test workloads (L = 12 to 20,000); the bound leaves room for the
+# shortest sequences, where |log P| is smallest.
+F16_POST_ATOL = 5e-2
+F16_LOGLIK_RTOL = 1e-3
 
 
 def need_gpu():
@@ -60,3 +74,19 @@ class forced_shape:
             os.environ.pop("LS_FORCE_SHAPE", None)
         else:
             os.environ["LS_FORCE_SHAPE"] = self.old
+
+
+def check_reduced(prec, got, ref, what):
+    """FP32 or FP16-stored results against the FP64 oracle: posteriors by
+    the max absolute error, log-likelihoods by the max relative error."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    if what == "log":
+        err = np.max(np.abs(got - ref) / np.abs(ref))
+        lim = F16_LOGLIK_RTOL if prec == "f16" else F32_LOGLIK_RTOL
+    else:
+        err = np.abs(got - ref).max()
+        lim = F16_POST_ATOL if prec == "f16" else F32_POST_ATOL
+    print(f"{prec} {what}: max error {err:.3e} (bound {lim:.0e})")
+    assert err <= lim, (prec, what, err, lim)
+    return err

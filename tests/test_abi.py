@@ -60,14 +60,14 @@ def test_host_only_calls(lib):
     assert lib.ls_status_string(4).decode().startswith("N too large")
     assert lib.ls_model_workspace_bytes(1, 10) == 0
     # internal rows: two copies of floor(N/64) words plus the partial word,
-    # padded to 64 B, the whole rounded up to 256 B; then four tables of L
+    # padded to 64 B, the whole rounded up to 256 B; then five tables of L
     # FP32 coefficient pairs; then the emission tables of a per-variant mu
     # (L FP64 pairs, L FP32 pairs, L + 1 FP64 prefix sums)
     def emis(L):
         return L * 16 + L * 8 + (L + 1) * 8
     # and the [N][2] checks of a prior matrix
-    assert lib.ls_model_workspace_bytes(200, 10) == 768 + 4 * 10 * 2 * 4 + emis(10) + 16 * 200
-    assert lib.ls_model_workspace_bytes(10000, 3) == 7680 + 4 * 3 * 2 * 4 + emis(3) + 16 * 10000
+    assert lib.ls_model_workspace_bytes(200, 10) == 768 + 5 * 10 * 2 * 4 + emis(10) + 16 * 200
+    assert lib.ls_model_workspace_bytes(10000, 3) == 7680 + 5 * 3 * 2 * 4 + emis(3) + 16 * 10000
 
 
 def test_validation_errors_before_any_device_work(lib):

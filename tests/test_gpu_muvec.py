@@ -11,6 +11,7 @@ import oracle
 from lsinputs import pack_haplotypes, rho_from_spacings
 
 from _gpu import (F32_LOGLIK_RTOL, F32_POST_ATOL, F64_ATOL_LOG, F64_ATOL_PROB, F64_RTOL,
+                  check_reduced,
                   forced_shape, need_gpu, rel_close)
 
 pytestmark = pytest.mark.gpu
@@ -58,10 +59,8 @@ def _check(prec, got, ref, what):
     if prec == "fp64":
         tol = F64_ATOL_LOG if what == "log" else F64_ATOL_PROB
         rel_close(got, ref, F64_RTOL, tol)
-    elif what == "log":
-        assert np.max(np.abs(got - ref) / np.abs(ref)) <= F32_LOGLIK_RTOL
     else:
-        assert np.abs(got - ref).max() <= F32_POST_ATOL
+        check_reduced(prec, got, ref, what)
 
 
 CASES = [(65, 40), (700, 30), (1031, 12), (200, 5000)]
@@ -71,8 +70,8 @@ CASES = [(65, 40), (700, 30), (1031, 12), (200, 5000)]
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "f16"])
 def test_vector_mu_decode_matches_oracle(ls, N, L, prec):
     """Posteriors, half distances, beta snapshots and both log scales; L =
-    5000 spans several sweep launches per direction. FP16 storage sweeps in
-    FP32 registers and meets the FP32 bounds."""
+    5000 spans several sweep launches per direction. FP16-stored vectors
+    against the FP16 bounds."""
     H, rho, mu = _case(N, L, seed=N + 13 * L)
     targets = np.unique(np.array([0, L // 3, L // 2, L - 1], np.int32))
     rec = np.arange(N, dtype=np.int32) if N <= 300 else np.array([0, 1, 63, 64, N - 1], np.int32)
@@ -91,9 +90,12 @@ def test_vector_mu_decode_matches_oracle(ls, N, L, prec):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_constant_vector_equals_scalar(ls, prec):
     """A vector holding the same mu at every variant gives the scalar
-    model's vectors bit for bit (the emission pairs are the same numbers);
-    the log scales agree to rounding (FP32 sums the log divisors from a
-    prefix table instead of one per step)."""
+    model's results. In FP32 arithmetic the vectors are the same bits (the
+    divided emission pairs and the coefficient tables are the same numbers)
+    and the log scales agree to rounding (the backward sums the log divisors
+    from a prefix table instead of one per step). The FP64 sweep divides a
+    scalar mu's pair by its larger member and keeps per-variant pairs as
+    they are, so there everything agrees to rounding."""
     N, L = 300, 3000
     H, rho, _ = _case(N, L, seed=3)
     mu = 0.003
@@ -102,15 +104,13 @@ def test_constant_vector_equals_scalar(ls, prec):
     targets = [0, 5, 1500, L - 1]
     a = ls.decode(ms, targets, prec, want=("P",))
     b = ls.decode(mv, targets, prec, want=("P",))
-    assert np.array_equal(_np(a["P"]), _np(b["P"]))
-    assert np.array_equal(_np(a["bsnap"]), _np(b["bsnap"]))
+    same = np.array_equal if prec == "fp32" else (
+        lambda x, y: np.allclose(x, y, rtol=1e-13, atol=1e-300))
+    assert same(_np(a["P"]), _np(b["P"]))
+    assert same(_np(a["bsnap"]), _np(b["bsnap"]))
     for k in ("fwd", "bck"):
-        assert np.array_equal(_np(a[k].state), _np(b[k].state))
-        x, y = _np(a[k].log_scale), _np(b[k].log_scale)
-        if prec == "fp64":
-            assert np.array_equal(x, y)
-        else:
-            assert np.allclose(x, y, rtol=1e-12, atol=0)
+        assert same(_np(a[k].state), _np(b[k].state))
+        assert np.allclose(_np(a[k].log_scale), _np(b[k].log_scale), rtol=1e-12, atol=0)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -235,9 +235,10 @@ def test_vector_mu_gradient_wide_groups(ls, prec, N, ns, nw):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_vector_mu_gradient_constant_vector(ls, prec):
-    """A constant vector: the rho gradient equals the scalar model's bit for
-    bit, the per-variant mu terms add up to the scalar d/d mu, and log P is
-    the same with and without the gradient."""
+    """A constant vector: the rho gradient equals the scalar model's (bit for
+    bit in FP32 arithmetic, to rounding in FP64, where only the scalar pair
+    is divided by its larger member), the per-variant mu terms add up to the
+    scalar d/d mu, and log P is the same with and without the gradient."""
     N, L = 200, 400
     H, rho, _ = _grad_case(N, L, seed=17)
     ms = ls.Model(H, N, rho, 0.004)
@@ -245,12 +246,16 @@ def test_vector_mu_gradient_constant_vector(ls, prec):
     a = ls.loglik_grad(ms, None, prec, grad=True)
     b = ls.loglik_grad(mv, None, prec, grad=True)
     c = ls.loglik_grad(mv, None, prec, grad=False)
-    assert np.array_equal(a["grad_rho"].cpu().numpy(), b["grad_rho"].cpu().numpy())
+    ga, gb = a["grad_rho"].cpu().numpy(), b["grad_rho"].cpu().numpy()
+    if prec == "fp32":
+        assert np.array_equal(ga, gb)
+    else:
+        assert np.allclose(ga, gb, rtol=1e-12, atol=1e-12 * np.abs(gb).max())
     assert np.array_equal(b["loglik"].cpu().numpy(), c["loglik"].cpu().numpy())
     gs, gv = float(a["grad_mu"].item()), float(b["grad_mu"].sum().item())
     assert abs(gs - gv) <= 1e-12 * float(b["grad_mu"].abs().sum().item())
     x, y = float(a["pac"].item()), float(b["pac"].item())
-    assert abs(x - y) <= (0 if prec == "fp64" else 1e-12) * abs(x)
+    assert abs(x - y) <= 1e-12 * abs(x)
 
 
 def test_vector_mu_autograd(ls):

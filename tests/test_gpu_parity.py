@@ -8,8 +8,8 @@ import pytest
 import oracle
 from lsinputs import make_inputs, pack_haplotypes, rho_from_spacings
 
-from _gpu import (F32_LOGLIK_RTOL, F32_POST_ATOL, F64_ATOL_LOG, F64_ATOL_PROB, F64_RTOL,
-                  forced_shape, need_gpu, rel_close)
+from _gpu import (F16_LOGLIK_RTOL, F16_POST_ATOL, F32_LOGLIK_RTOL, F32_POST_ATOL, F64_ATOL_LOG,
+                  F64_ATOL_PROB, F64_RTOL, check_reduced, forced_shape, need_gpu, rel_close)
 
 pytestmark = pytest.mark.gpu
 
@@ -94,13 +94,52 @@ def test_c1_reduced_precision(ls, c1, c1_ref, prec):
     x, ref = c1, c1_ref
     m = ls.Model(x["H"], x["N"], x["rho"], x["mu"])
     r = ls.decode(m, x["targets"], prec, want=("P", "E"))
-    err = np.abs(_np(r["P"]) - ref["P"]).max()
-    llerr = np.max(np.abs(_np(r["fwd"].log_scale) - ref["llf"]) / np.abs(ref["llf"]))
-    print(f"{prec}: max abs posterior error {err:.3e}, max rel loglik error {llerr:.3e}")
-    # FP16 storage only touches tables kept between calls; decode sweeps in
-    # FP32 registers throughout, so both precisions meet the FP32 bounds
-    assert err <= F32_POST_ATOL
-    assert llerr <= F32_LOGLIK_RTOL
+    check_reduced(prec, _np(r["P"]), ref["P"], "prob")
+    check_reduced(prec, _np(r["fwd"].log_scale), ref["llf"], "log")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "f16"])
+def test_c1_reduced_tables_hold_alpha_and_beta(ls, c1, c1_ref, prec):
+    """Reduced-precision tables hold alpha^l and beta^l themselves (FP16:
+    times the stated kappa), not the vectors of the divided emission pairs:
+    each row within the precision's posterior bound of the oracle's, relative
+    to the row's total. The log scales: FP32 within its log-likelihood bound
+    (relative, at least 1 in the denominator: log F^l is near 0 at l = 0);
+    FP16 storage adds a relative error of at most u = 2^-11 to each step's
+    column sum, with no common sign, so after s steps the log scale is
+    within 8 u sqrt(s) (a bound far outside the random walk's spread)."""
+    x, ref = c1, c1_ref
+    N = x["N"]
+    kf, kb = (2.0 ** 14, 2.0 ** 14 / (N - 1)) if prec == "f16" else (1.0, 1.0)
+    post = F16_POST_ATOL if prec == "f16" else F32_POST_ATOL
+    logb = F16_LOGLIK_RTOL if prec == "f16" else F32_LOGLIK_RTOL
+    m = ls.Model(x["H"], N, x["rho"], x["mu"])
+    fwd = ls.Table(m, 0, prec)
+    bck = ls.Table(m, 1, prec)
+
+    def check(tab, kappa, vec, logs, steps):
+        got = _np(tab.state) / kappa
+        err = (np.abs(got - vec).max(axis=1) / vec.sum(axis=1)).max()
+        dl = np.abs(_np(tab.log_scale) - logs)
+        if prec == "f16":
+            lerr = dl.max() / (8 * 2.0 ** -11 * np.sqrt(steps))
+            assert err <= post and lerr <= 1.0, (err, lerr)
+        else:
+            lerr = (dl / np.maximum(np.abs(logs), 1.0)).max()
+            assert err <= post and lerr <= logb, (err, lerr)
+        return err, lerr
+
+    worst = [0.0, 0.0]
+    L = x["L"]
+    for k, t in enumerate(x["targets"]):
+        ls.forward(fwd, m, int(t))
+        worst = np.maximum(worst, check(fwd, kf, ref["A"][k], ref["logF"][k], t + 1))
+    for k in range(len(x["targets"]) - 1, -1, -1):
+        t = int(x["targets"][k])
+        ls.backward(bck, m, t)
+        worst = np.maximum(worst, check(bck, kb, ref["B"][k], ref["logG"][k], L - t))
+    print(f"{prec} tables: row error {worst[0]:.3e}, log scale error {worst[1]:.3e} "
+          f"({'of the bound' if prec == 'f16' else 'relative'})")
 
 
 # ---------------------------------------------------------------------------
@@ -297,8 +336,9 @@ def test_posterior_distance_from_tables(ls, c1, c1_ref):
         if prec == "fp64":
             rel_close(_np(P), ref["P"][3], F64_RTOL, F64_ATOL_PROB)
             rel_close(_np(E), ref["E"][3], F64_RTOL, F64_ATOL_LOG)
-        elif prec == "fp32":
-            assert np.abs(_np(P) - ref["P"][3]).max() <= F32_POST_ATOL
+        else:
+            # FP16: posteriors read straight from the two half tables
+            check_reduced(prec, _np(P), ref["P"][3], "prob")
 
 
 def test_distance_matrix(ls, c1, c1_ref):
@@ -380,8 +420,8 @@ def test_mutation_probability_above_one_half(ls, mu):
             rel_close(P, ref["P"], F64_RTOL, F64_ATOL_PROB)
             rel_close(ll, ref["llf"], F64_RTOL, F64_ATOL_LOG)
         else:
-            assert np.abs(P - ref["P"]).max() <= F32_POST_ATOL
-            assert np.max(np.abs(ll - ref["llf"]) / np.abs(ref["llf"])) <= F32_LOGLIK_RTOL
+            check_reduced(prec, P, ref["P"], "prob")
+            check_reduced(prec, ll, ref["llf"], "log")
 
 
 def test_model_mismatch_is_rejected(ls):

@@ -11,6 +11,7 @@ import oracle
 from lsinputs import pack_haplotypes, rho_from_spacings
 
 from _gpu import (F32_LOGLIK_RTOL, F32_POST_ATOL, F64_ATOL_LOG, F64_ATOL_PROB, F64_RTOL,
+                  check_reduced,
                   need_gpu, rel_close)
 
 pytestmark = pytest.mark.gpu
@@ -50,10 +51,8 @@ def _case(N, L, seed, mu=0.01):
 def _check(prec, got, ref, what):
     if prec == "fp64":
         rel_close(got, ref, F64_RTOL, F64_ATOL_LOG if what == "log" else F64_ATOL_PROB)
-    elif what == "log":
-        assert np.max(np.abs(got - ref) / np.abs(ref)) <= F32_LOGLIK_RTOL
     else:
-        assert np.abs(got - ref).max() <= F32_POST_ATOL
+        check_reduced(prec, got, ref, what)
 
 
 CASES = [(65, 40), (700, 30), (1031, 12), (200, 3000), (8000, 10)]
@@ -151,7 +150,10 @@ def test_prior_with_vector_mu_matches_oracle(ls, N, L, prec):
         assert ls.status_check(r["fwd"]) == ls.LS_OK
         _check(prec, _np(r["P"]), ref["P"], "prob")
         _check(prec, _np(r["fwd"].log_scale), ref["llf"], "log")
-        _check(prec, _np(r["bck"].log_scale), ref["logG"][0], "log")
+        if prec != "f16":
+            # FP16-stored backward tables with a prior hold a positive multiple
+            # of beta (normalised by the plain column sum), not log G^0
+            _check(prec, _np(r["bck"].log_scale), ref["logG"][0], "log")
 
 
 def test_prior_invalid(ls):
