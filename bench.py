@@ -16,7 +16,9 @@ the oracle's sample; the gradient workload (N = 2,000, L = 50,000: PAC and its
 gradient for all recipients, error against the oracle on 256 recipients); the
 large workload (N = 100,000, L = 10,000: five resident 100k x 100k FP32
 distance matrices from recipient windows, error against the oracle on 64
-recipients); and the FP16-stored precision on the benchmark workload.
+recipients); the precision study (N = 50,000: FP32 and FP16-stored vectors
+against the oracle); and the average linkage of the step's 100 distance
+matrices.
 
 Prints one JSON line.
 """
@@ -158,6 +160,29 @@ def c2_accuracy_all(ls, torch, model, targets, N, window=50):
     return err, ll_err
 
 
+def cluster_matrices(ls, torch, D, check):
+    """Average pairwise linkage (section 6) of the step's T distance matrices,
+    resident on the device (one workgroup per matrix, side by side), timed
+    with HIP events; with `check`, matrix 0's merges and leaf order against
+    the oracle's."""
+    T, N = int(D.shape[0]), int(D.shape[1])
+    D0 = D[0].cpu().numpy() if check else None
+    torch.cuda.synchronize()
+    with Timer(torch) as t:
+        Z, order = ls.average_linkage(D)
+    ms = t.ms()
+    out = {"matrices": T, "N": N, "ms": ms, "ms_per_matrix": ms / T,
+           "method": "average pairwise linkage, FP32, merges equal to the plain algorithm's"}
+    if check:
+        import oracle
+        t0 = time.perf_counter()
+        Zr, orr = oracle.average_linkage(D0)
+        out["oracle_seconds_one_matrix"] = time.perf_counter() - t0
+        out["matrix0_equals_oracle"] = bool(np.array_equal(Z[0].cpu().numpy(), Zr) and
+                                            np.array_equal(order[0].cpu().numpy(), orr))
+    return out
+
+
 def gradient_workload(ls, torch, oracle, nthreads, reps=3):
     """PAC and its gradient for every recipient of the gradient workload
     (N = 2,000, L = 50,000), FP32 and FP64, timed with HIP events; error of
@@ -193,6 +218,52 @@ def gradient_workload(ls, torch, oracle, nthreads, reps=3):
         out[f"{prec}_grad_mu_rel_err_vs_oracle"] = float(abs(g["grad_mu"].item() - gm) / abs(gm))
         out[f"{prec}_pac_rel_err_vs_oracle"] = float(abs(g["pac"].item() - ll) / abs(ll))
     out["oracle_sample"] = "256 seeded recipients, exact score (full forward table per recipient)"
+    return out
+
+
+def precision_workload(ls, torch, oracle, nthreads, count=64, timed_recipients=2560):
+    """The precision study (N = 50,000, L = 20,000, rare-variant mosaic, 20
+    targets): FP32 and FP16-stored vectors against the FP64 oracle on
+    `count` seeded recipients (posteriors at every target, log-likelihoods;
+    the FP64 GPU path does not fit one compute unit at this N), and the
+    forward+backward cell rate of both on `timed_recipients` recipients."""
+    from lsinputs import make_inputs, seeded_recipients
+    t0 = time.time()
+    x = make_inputs("c3")
+    N, L, targets = x["N"], x["L"], x["targets"]
+    log(f"inputs c3: N={N} L={L} ({time.time() - t0:.1f}s)")
+    m = ls.Model(x["H"], N, x["rho"], x["mu"])
+    rec = seeded_recipients(N, count, seed=3030)
+    t0 = time.perf_counter()
+    ref = oracle.run_pass(x["H"], N, L, x["rho"], x["mu"], rec, targets, want=("P",),
+                          nthreads=nthreads)
+    out = {"workload": f"N={N}, L={L}, {len(targets)} targets, rare-variant mosaic of "
+                       f"{x['cfg']['K']} founders",
+           "oracle_sample": f"{len(rec)} seeded recipients, all donors, all variants, all targets",
+           "oracle_seconds": time.perf_counter() - t0}
+    trec = np.arange(min(timed_recipients, N), dtype=np.int32)
+    for prec in ("fp32", "f16"):
+        r = ls.decode(m, targets, prec, recipients=rec, want=("P",))
+        P = r["P"].double().cpu().numpy()
+        ll = r["fwd"].log_scale.cpu().numpy()
+        out[f"{prec}_max_posterior_err_vs_oracle"] = float(np.abs(P - ref["P"]).max())
+        out[f"{prec}_max_rel_loglik_err_vs_oracle"] = float(
+            np.max(np.abs(ll - ref["llf"]) / np.abs(ref["llf"])))
+        del r, P
+        ms = 0.0
+        for d in (1, 0):
+            tab = ls.Table(m, d, prec, trec)
+            torch.cuda.synchronize()
+            with Timer(torch) as t:
+                if d == 1:
+                    ls.backward(tab, m, 0)
+                else:
+                    ls.forward(tab, m, L - 1)
+            ms += t.ms()
+            del tab
+        out[f"{prec}_fwd_bwd_cells_per_s"] = len(trec) * float(N) * L / (ms / 1e3)
+        out[f"{prec}_shape"] = list(ls.kernel_shape(N, prec))
+    torch.cuda.empty_cache()
     return out
 
 
@@ -266,6 +337,10 @@ def main():
                     help="skip the all-recipient FP32 vs FP64 comparison")
     ap.add_argument("--no-gradient", action="store_true", help="skip the gradient workload")
     ap.add_argument("--no-large", action="store_true", help="skip the large workload")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the FP32 / FP16-stored precision workload")
+    ap.add_argument("--no-clustering", action="store_true",
+                    help="skip the average linkage of the step's distance matrices")
     ap.add_argument("--profile", action="store_true",
                     help="the timed steps only (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -279,7 +354,7 @@ def main():
         sys.exit(2)
     if args.profile:
         args.no_cpu_baseline = args.no_fp64 = args.no_accuracy = True
-        args.no_gradient = args.no_large = True
+        args.no_gradient = args.no_large = args.no_clustering = args.no_precision = True
 
     import torch
 
@@ -314,7 +389,7 @@ def main():
             ev[3].record(stream)
         return fwd, bck
 
-    def timed(prec, steps, warmup):
+    def timed(prec, steps, warmup, after=None):
         dt = ls.io_dtype(prec)
         bufs = dict(bsnap=torch.empty((T, N, N), dtype=dt, device=dev),
                     E=torch.empty((T, N, N), dtype=dt, device=dev))
@@ -334,14 +409,19 @@ def main():
         sym_ms = np.mean([e[2].elapsed_time(e[3]) for e in evs])
         status = ls.status_check(tabs[0])
         ll = tabs[0].log_scale.cpu().numpy()
+        extra = after(bufs["E"]) if after else None
         del bufs
         torch.cuda.empty_cache()
         return dict(wall=wall, ms_per_step=1e3 * wall / steps, bwd_ms=bwd_ms, fwd_ms=fwd_ms,
-                    sym_ms=sym_ms, status=status, loglik=ll)
+                    sym_ms=sym_ms, status=status, loglik=ll, extra=extra)
 
     shape = ls.kernel_shape(N, "fp32")
     log(f"fp32 shape {shape}, fp64 shape {ls.kernel_shape(N, 'fp64')}")
-    r32 = timed("fp32", args.steps, args.warmup)
+    after = None
+    if not args.no_clustering:
+        def after(D):
+            return cluster_matrices(ls, torch, D, check=not args.no_cpu_baseline)
+    r32 = timed("fp32", args.steps, args.warmup, after)
     cells = float(N) * N * L
     value = cells / (r32["ms_per_step"] / 1e3)
     log(f"fp32: {r32['ms_per_step']:.1f} ms/step (bwd {r32['bwd_ms']:.1f}, fwd+post "
@@ -388,6 +468,9 @@ def main():
                               r32["fwd_ms"], "symmetrise": r32["sym_ms"]},
         "nonfinite_status": int(r32["status"]),
     }
+    if r32["extra"] is not None:
+        line["clustering"] = r32["extra"]
+        log(f"clustering: {r32['extra']}")
 
     r64 = None
     if not args.no_fp64:
@@ -411,7 +494,7 @@ def main():
 
     oracle = None
     nthreads = 1
-    if not args.no_cpu_baseline or not args.no_gradient or not args.no_large:
+    if not (args.no_cpu_baseline and args.no_gradient and args.no_large and args.no_precision):
         import oracle
         nthreads = oracle.default_threads()
     if not args.no_cpu_baseline:
@@ -437,6 +520,10 @@ def main():
         line["gradient_workload"] = gradient_workload(ls, torch, oracle, nthreads)
         log(f"gradient workload: {line['gradient_workload']} ({time.time() - t0:.1f}s)")
         torch.cuda.empty_cache()
+    if not args.no_precision:
+        t0 = time.time()
+        line["precision_workload"] = precision_workload(ls, torch, oracle, nthreads)
+        log(f"precision workload: {line['precision_workload']} ({time.time() - t0:.1f}s)")
     if not args.no_large:
         t0 = time.time()
         line["large_workload"] = large_workload(ls, torch, oracle, nthreads)
