@@ -105,21 +105,26 @@ bool shape_fits(int32_t N, int prec, int nslot, int nwaves, bool prior = false) 
 }
 
 // Relative time of one recipient step for a shape, from a cost model fitted
-// to measured sweep times on MI355X (N = 2,000 .. 100,000, both precisions,
-// all recipients): the VALU work of the step (per slot and per wave) over all
-// waves of the group, inflated when a SIMD holds fewer waves than it needs to
-// hide the per-step load, reduction and barrier latency, and by the uneven
-// spread of the group's waves over the four SIMDs of a compute unit (every
-// step ends in a barrier, so the busiest SIMD sets the pace).
-double shape_cost(int32_t N, int prec, int ns, int nw, int wps = 0) {
+// to measured sweep times on MI355X: the VALU work of the step (per slot and
+// per wave) over all waves of the group, inflated when a SIMD holds fewer
+// waves than it needs to hide the per-step load, reduction and barrier
+// latency, and by the uneven spread of the group's waves over the four SIMDs
+// of a compute unit (every step ends in a barrier, so the busiest SIMD sets
+// the pace). FP32-arithmetic sweeps (masked emission: three vector
+// instructions per slot) were fitted to every shape that places N at
+// N = 1,000 .. 100,000 (130 shapes, forward and backward); the FP64 sweep,
+// sweeps with a prior matrix and the gradient keep the parameters fitted
+// earlier (N = 2,000 .. 100,000, 38 shapes).
+double shape_cost(int32_t N, int prec, int ns, int nw, int wps = 0, bool sweep = true) {
     const bool f64 = prec == LS_FP64;
+    const bool masked = !f64 && sweep;
     if (wps <= 0) wps = lsk::sweep_waves_per_simd(ns, vgpr_per_slot(prec));
     // waves resident per SIMD when all N recipients are swept
     const double occ = std::min<double>(wps, (double)N * nw / 1024.0);
-    const double ops = (f64 ? 4.19 : 4.0) * ns + 60.7;
-    const double hide = f64 ? 3.34 : 5.57;
+    const double ops = masked ? 2.5 * ns + 40.0 : (f64 ? 4.19 : 4.0) * ns + 60.7;
+    const double hide = masked ? 5.0 : (f64 ? 3.34 : 5.57);
     const double imb = nw >= 4 ? ((nw + 3) / 4) / (nw / 4.0) : 1.0;
-    return (double)nw * ops * std::max(1.0, hide / occ) * std::pow(imb, 0.847);
+    return (double)nw * ops * std::max(1.0, hide / occ) * std::pow(imb, masked ? 1.5 : 0.847);
 }
 
 // Cheapest shape by shape_cost; among shapes within 1% of the cheapest, the
@@ -145,7 +150,7 @@ bool choose_shape(int32_t N, int prec, Shape *out, bool grad = false, bool prior
         auto cost = [&](int ns, int nw) {
             const int wps = pass == 0 ? lsk::grad_waves_per_simd(ns, vps, prior)
                                       : lsk::sweep_waves_per_simd(ns, lsk::sweep_slot_vgprs(vps, prior));
-            return shape_cost(N, prec, ns, nw, wps);
+            return shape_cost(N, prec, ns, nw, wps, !grad && !prior);
         };
         double best = 1e300;
         for (int nw = 1; nw <= lsk::kMaxWaves; ++nw)

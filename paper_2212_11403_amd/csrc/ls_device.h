@@ -402,24 +402,50 @@ LS_XM_DEFINE(double, "v_mul_f64")
 #undef LS_XM8
 #undef LS_XM
 
+// Makes the 24 row words of a group live in scalar registers at this point,
+// so that their loads are issued together and waited for once. Scalar loads
+// return out of order, so every wait for one of them waits for all; left to
+// itself the scheduler of the widest kernels (high vector register pressure)
+// issues one 8-word load at a time and waits for each, a round trip per 8
+// slots and step.
+__device__ __forceinline__ void sgpr_group24(const uint64_t (&m)[24]) {
+    asm volatile("" ::"s"(m[0]), "s"(m[1]), "s"(m[2]), "s"(m[3]), "s"(m[4]), "s"(m[5]),
+                 "s"(m[6]), "s"(m[7]), "s"(m[8]), "s"(m[9]), "s"(m[10]), "s"(m[11]),
+                 "s"(m[12]), "s"(m[13]), "s"(m[14]), "s"(m[15]), "s"(m[16]), "s"(m[17]),
+                 "s"(m[18]), "s"(m[19]), "s"(m[20]), "s"(m[21]), "s"(m[22]), "s"(m[23]));
+}
+
 // v[s] <- r v[s] on the lanes of (mask(s) ^ flip), s < NS, in blocks of
-// 8, 4 and 1 slots; the last block carries the DPP wait states.
+// 8, 4 and 1 slots; the last block carries the DPP wait states. From 64
+// slots up the 8-slot blocks go in groups of three whose row words are
+// loaded together (sgpr_group24).
 template <int NS, class T, class MaskFn>
 __device__ __forceinline__ void masked_scale_all(T (&v)[NS], MaskFn mask, uint64_t flip, T r) {
     constexpr int N8 = NS / 8, N4 = (NS % 8) / 4, N1 = NS % 4;
+    constexpr int G = NS >= 64 ? 3 : 1;  // 8-slot blocks per load group
 #pragma unroll
-    for (int q = 0; q < N8; ++q) {
-        T x[8];
-        uint64_t m[8];
+    for (int q0 = 0; q0 < N8; q0 += G) {
+        const int ng = (N8 - q0) < G ? (N8 - q0) : G;
+        uint64_t m[24];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            x[k] = v[8 * q + k];
-            m[k] = mask(8 * q + k);
+        for (int k = 0; k < 24; ++k) m[k] = k < 8 * ng ? mask(8 * q0 + k) : 0ull;
+        if (G > 1 && ng == G) sgpr_group24(m);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (g >= ng) break;
+            const int q = q0 + g;
+            T x[8];
+            uint64_t mm[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                x[k] = v[8 * q + k];
+                mm[k] = m[8 * g + k];
+            }
+            if (q == N8 - 1 && N4 == 0 && N1 == 0) masked_scale8<true>(x, mm, flip, r);
+            else masked_scale8<false>(x, mm, flip, r);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[8 * q + k] = x[k];
         }
-        if (q == N8 - 1 && N4 == 0 && N1 == 0) masked_scale8<true>(x, m, flip, r);
-        else masked_scale8<false>(x, m, flip, r);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) v[8 * q + k] = x[k];
     }
     if constexpr (N4 > 0) {
         T x[4];
