@@ -57,6 +57,8 @@ typedef enum {
                                feature this precision does not offer */
     LS_ERR_DEVICE = 5,      /* the HIP runtime reported an error */
     LS_ERR_WORKSPACE = 6,   /* workspace missing or too small */
+    LS_ERR_SCRATCH = 7,     /* request larger than the fixed scratch of an
+                               allocation-free call (nothing launched) */
     LS_WARN_NONFINITE = 16  /* returned by ls_status_check only */
 } ls_status;
 
@@ -271,6 +273,22 @@ ls_status ls_distance_symmetrise(const void *E, void *D, int32_t N, int32_t T,
 size_t ls_average_linkage_workspace_bytes(int32_t N, int32_t T, ls_precision prec);
 ls_status ls_average_linkage(void *D, int32_t N, int32_t T, ls_precision prec, double *Z,
                              int32_t *order, void *workspace, size_t ws_bytes, void *stream);
+
+/* ls_average_linkage for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid it):
+ * the same kernels and results, with the workspace taken from a fixed
+ * 32 MiB scratch array the library holds on each GPU until the process ends
+ * (enough for N = 10,000 with up to 150 matrices, or N = 100,000 with up to
+ * 15). The call allocates nothing; the caller passes D, Z and order as for
+ * ls_average_linkage. Every call on one GPU uses that GPU's array: calls
+ * that overlap on one GPU (other streams or threads) race and must be
+ * ordered by the caller. The array needs no clearing (every entry a call
+ * reads it first writes).
+ * Errors: LS_ERR_ARG; LS_ERR_SCRATCH when
+ * ls_average_linkage_workspace_bytes(N, T, prec) exceeds 32 MiB (nothing is
+ * launched); LS_ERR_DEVICE. */
+ls_status ls_average_linkage_noalloc(void *D, int32_t N, int32_t T, ls_precision prec, double *Z,
+                                     int32_t *order, void *stream);
 
 /* Standardised half-distance rows (section 2.2: a recipient's column of
  * distances standardised, with 0 where its deviation is 0), in place: row

@@ -15,7 +15,7 @@ __all__ = [
     "LsError", "load", "Model", "Table", "forward", "backward", "posterior_distance",
     "distance_symmetrise", "loglik_grad", "kernel_shape", "status_check", "decode",
     "PACLoglik", "RhoMap", "calc_rho", "rho_map_grad", "distance_matrices", "average_linkage",
-    "standardise_rows",
+    "average_linkage_noalloc", "standardise_rows",
 ]
 
 
@@ -25,7 +25,7 @@ def __getattr__(name):
     if name in ("Model", "Table", "forward", "backward", "posterior_distance",
                 "distance_symmetrise", "loglik_grad", "kernel_shape", "status_check", "decode",
                 "io_dtype", "prec_code", "calc_rho", "rho_map_grad", "distance_matrices",
-                "average_linkage", "standardise_rows"):
+                "average_linkage", "average_linkage_noalloc", "standardise_rows"):
         from . import api
         return getattr(api, name)
     if name in ("PACLoglik", "RhoMap"):

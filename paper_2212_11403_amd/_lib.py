@@ -15,6 +15,7 @@ LS_ERR_STATE = 3
 LS_ERR_UNSUPPORTED = 4
 LS_ERR_DEVICE = 5
 LS_ERR_WORKSPACE = 6
+LS_ERR_SCRATCH = 7
 LS_WARN_NONFINITE = 16
 
 LS_FP64 = 0
@@ -32,7 +33,7 @@ EXPORTED = [
     "ls_loglik_grad", "ls_loglik_grad_workspace_bytes", "ls_status_check",
     "ls_kernel_shape", "ls_status_string", "ls_version", "ls_calc_rho", "ls_rho_map_grad",
     "ls_loglik_checkpoint", "ls_loglik_grad_adjoint", "ls_average_linkage",
-    "ls_average_linkage_workspace_bytes", "ls_standardise_rows",
+    "ls_average_linkage_workspace_bytes", "ls_average_linkage_noalloc", "ls_standardise_rows",
 ]
 
 
@@ -114,6 +115,7 @@ def load():
         "ls_loglik_checkpoint": (ctypes.c_int, [M, P, I32, ctypes.c_int, P, P, P, SZ, P]),
         "ls_average_linkage_workspace_bytes": (SZ, [I32, I32, ctypes.c_int]),
         "ls_average_linkage": (ctypes.c_int, [P, I32, I32, ctypes.c_int, P, P, P, SZ, P]),
+        "ls_average_linkage_noalloc": (ctypes.c_int, [P, I32, I32, ctypes.c_int, P, P, P]),
         "ls_standardise_rows": (ctypes.c_int, [P, P, I32, I32, I32, I64, I64, ctypes.c_int, P]),
         "ls_loglik_grad_adjoint": (ctypes.c_int, [M, P, I32, ctypes.c_int, P, P, P, SZ, P]),
         "ls_status_check": (ctypes.c_int, [P, I32, P]),

@@ -447,6 +447,32 @@ def average_linkage(D: torch.Tensor, prec=None, order: bool = True, stream=None)
     return Z, o
 
 
+def average_linkage_noalloc(D: torch.Tensor, Z: torch.Tensor, order: torch.Tensor = None,
+                            prec=None, stream=None):
+    """average_linkage into caller-provided outputs through the entry point
+    that allocates nothing (ls_average_linkage_noalloc: the workspace is the
+    library's fixed per-device scratch). D [T][N][N] (overwritten), Z
+    [T][N-1][4] float64, order [T][N] int32 or None; nothing is allocated
+    here either. Calls on one GPU share the scratch and must not overlap."""
+    if D.dim() != 3 or not D.is_contiguous() or D.shape[-1] != D.shape[-2]:
+        raise ValueError("D must be contiguous [T][N][N]")
+    T, N = int(D.shape[0]), int(D.shape[-1])
+    if prec is None:
+        prec = "fp64" if D.dtype == torch.float64 else "fp32"
+    pc = prec_code(prec)
+    if (D.dtype == torch.float64) != (pc == LS_FP64):
+        raise ValueError("D's dtype does not match the precision")
+    if N > 1 and (Z.dtype != torch.float64 or tuple(Z.shape) != (T, N - 1, 4)
+                  or not Z.is_contiguous()):
+        raise ValueError("Z must be contiguous float64 [T][N-1][4]")
+    if order is not None and (order.dtype != torch.int32 or tuple(order.shape) != (T, N)
+                              or not order.is_contiguous()):
+        raise ValueError("order must be contiguous int32 [T][N]")
+    check(_lib.load().ls_average_linkage_noalloc(_p(D), N, T, pc, _p(Z) if N > 1 else None,
+                                                 _p(order), _stream(stream)),
+          "ls_average_linkage_noalloc")
+
+
 def standardise_rows(E: torch.Tensor, recipients, prec=None, stream=None,
                      out_strides=(0, 0), N=None) -> torch.Tensor:
     """Standardise half-distance rows in place (section 2.2): E [T][R][N]

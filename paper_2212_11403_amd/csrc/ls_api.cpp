@@ -655,6 +655,18 @@ ls_status ls_average_linkage(void *D, int32_t N, int32_t T, ls_precision prec, d
                                    as_stream(stream)));
 }
 
+ls_status ls_average_linkage_noalloc(void *D, int32_t N, int32_t T, ls_precision prec, double *Z,
+                                     int32_t *order, void *stream) {
+    clear_stale_hip_error();
+    if (!D || N < 1 || T < 1 || !valid_prec(prec) || (N > 1 && !Z)) return LS_ERR_ARG;
+    if (T > 0x7fffffff / 1024) return LS_ERR_ARG;
+    if (lsk::linkage_workspace_bytes(N, T, prec == LS_FP64) > lsk::kLinkageScratchBytes)
+        return LS_ERR_SCRATCH;
+    void *ws = nullptr;
+    if (lsk::linkage_scratch(&ws) != hipSuccess) return LS_ERR_DEVICE;
+    return dev(lsk::launch_linkage(D, N, T, prec == LS_FP64, Z, order, ws, as_stream(stream)));
+}
+
 ls_status ls_standardise_rows(void *E, const int32_t *recipients, int32_t R, int32_t T,
                               int32_t N, int64_t out_target_stride, int64_t out_row_stride,
                               ls_precision prec, void *stream) {
@@ -836,6 +848,7 @@ const char *ls_status_string(ls_status s) {
     case LS_ERR_UNSUPPORTED: return "N too large for this precision on one GPU, or not offered in it";
     case LS_ERR_DEVICE: return "HIP runtime error";
     case LS_ERR_WORKSPACE: return "workspace missing or too small";
+    case LS_ERR_SCRATCH: return "request larger than the fixed scratch of an allocation-free call";
     case LS_WARN_NONFINITE: return "a column sum was zero or non-finite";
     }
     return "unknown status";

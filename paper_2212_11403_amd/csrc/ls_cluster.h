@@ -21,4 +21,10 @@ hipError_t launch_linkage(void *D, int32_t N, int32_t T, int is_f64, double *Z, 
 hipError_t launch_standardise(void *E, const int32_t *recips, int32_t R, int32_t T, int32_t N,
                               int64_t ts, int64_t rs, int is_f64, hipStream_t st);
 
+// Size of the fixed per-device scratch of the allocation-free linkage entry
+// point (enough for N = 10,000 with T = 150 matrices, or N = 100,000 with
+// T = 15), and the address of the current device's copy (ls_cluster.hip).
+constexpr size_t kLinkageScratchBytes = (size_t)32 << 20;
+hipError_t linkage_scratch(void **out);
+
 }  // namespace lsk

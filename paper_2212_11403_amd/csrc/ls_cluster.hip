@@ -18,6 +18,8 @@
 // are rescanned; every other row only compares its new distance to a.
 #include <math.h>
 
+#include <mutex>
+
 #include "ls_cluster.h"
 #include "ls_device.h"
 
@@ -340,6 +342,36 @@ hipError_t launch_standardise(void *E, const int32_t *recips, int32_t R, int32_t
         hipLaunchKernelGGL(standardise_kernel<float>, grid, dim3(256), 0, st, (float *)E, recips,
                            N, ts, rs);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed scratch of the allocation-free linkage entry point: a file-scope
+// device array, one copy per GPU, held until the process ends. In host code
+// its name is not a device address; the address of each GPU's copy comes
+// from hipGetSymbolAddress with that GPU current, taken once per GPU on its
+// first use and kept.
+static __device__ __align__(256) char scratch[kLinkageScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t linkage_scratch(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace lsk
