@@ -43,13 +43,14 @@ FP64_PEAK = 78.6e12
 # Algorithmic flops per cell and direction: FMA (2) + MUL + ADD; the emission
 # select is not a flop.
 FLOPS_PER_CELL = 4
-# Issue ceiling of the VALU in FP32 lane-operations/s: the FP32 peak above at
-# two flops per FMA, i.e. 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz (two wave64
-# instructions per SIMD every four cycles; one wave64 instruction per four
-# cycles would be half of it). The sweep issues 4 lane-operations per cell:
-# select, FMA, MUL, ADD.
+# Issue ceiling of the VALU in lane-instructions/s: 256 CUs x 4 SIMDs x 32
+# lanes x 2.4 GHz, i.e. two wave64 instructions per SIMD every four cycles
+# (the sweep's VALU counters show more than one per four cycles). The
+# masked-emission sweep needs 3 lane-instructions per cell: FMA, the
+# EXEC-masked multiply (one instruction per 64 cells whatever the mask) and
+# the column-sum ADD.
 ISSUE_PEAK = 256 * 4 * 32 * 2.4e9
-ISSUE_OPS_PER_CELL = 4
+ISSUE_OPS_PER_CELL = 3
 HBM_PEAK = 8.0e12
 SWEEP_CHUNK = 2048  # variants per sweep launch (the library splits longer sweeps)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_bwd_fp32_c2_traffic.txt")
