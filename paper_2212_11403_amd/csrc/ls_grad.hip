@@ -212,14 +212,12 @@ hipError_t launch_grad(const GradArgs &ga, int prec, Shape sh, double *loglik, d
         const int s0 = k * ga.seg;
         const int s1 = std::min(s0 + ga.seg - 1, ga.L - 1);
         if (s1 > s0) {
-            // recompute alpha^{s0+1..s1} from the checkpoint (a copy, so the
-            // checkpoint itself stays for the adjoint pass)
-            e = hipMemcpyAsync(fstate, ws + Ly.off_ckpt + (size_t)k * RN * es, (size_t)RN * es,
-                               hipMemcpyDeviceToDevice, st);
-            if (e != hipSuccess) return e;
-            // alpha^{s0+1..s1} into segment rows 0 .. s1-s0-1
+            // recompute alpha^{s0+1..s1} into segment rows 0 .. s1-s0-1,
+            // starting from the checkpoint itself (the keep-alpha sweep only
+            // reads its table, so the checkpoint stays for the adjoint pass)
             const int32_t out0 = 0;
-            e = sweep(0, s0, s1, &out0, 0, fstate, ws + Ly.off_seg, scratch, true);
+            e = sweep(0, s0, s1, &out0, 0, ws + Ly.off_ckpt + (size_t)k * RN * es, ws + Ly.off_seg,
+                      scratch, true);
             if (e != hipSuccess) return e;
         }
         GradSegArgs sa;

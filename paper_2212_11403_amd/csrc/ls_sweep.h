@@ -113,8 +113,11 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
     constexpr int NR = NSLOT - K;
     constexpr int MAXW = max_waves_for(NSLOT, sweep_slot_vgprs(PT::vgpr_per_slot, PI));
     // emission as a lane-masked multiply (every sweep whose emission pairs
-    // have a member equal to 1: all but FP64 with a per-variant mu)
-    constexpr bool XMUL = !(MUV && sizeof(T) == 8);
+    // have a member equal to 1: all but FP64 with a per-variant mu), except
+    // the gradient's keep-alpha recompute, where the select form measured
+    // faster (its 8-slot groups store every step's vector: 0.43 against
+    // 0.49 ms per segment in FP32 at N = 2,000, and the same in FP64)
+    constexpr bool XMUL = !(MUV && sizeof(T) == 8) && !EVERY;
     // FP16-stored vectors: rounded to half after every update
     constexpr bool QH = std::is_same<ST, _Float16>::value;
     // the FP16-stored backward with a prior matrix normalises by the plain
@@ -661,7 +664,9 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
             }
         }
     }
-    store_state();
+    // the keep-alpha recompute reads its start vector from a checkpoint that
+    // the adjoint pass needs unchanged, and nothing reads its final vector
+    if constexpr (!EVERY) store_state();
     // ---- epilogue: log scale and status ------------------------------------
     if (threadIdx.x == 0) {
         double ls = base + (log(prod) + (double)expo * 0.69314718055994530942) +
