@@ -79,6 +79,9 @@ def _compile(src: str, force: bool, keep_asm: bool):
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {os.path.basename(src)}:\n{r.stderr[-4000:]}")
     os.replace(obj + ".tmp", obj)
+    # date the object by when the compile started, so that a source edited
+    # while it compiled still counts as newer next time
+    os.utime(obj, (t0, t0))
     noise = "\n".join(line for line in r.stderr.splitlines() if "packed-fp32-ops" not in line)
     return obj, time.time() - t0, noise
 

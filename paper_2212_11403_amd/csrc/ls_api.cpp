@@ -110,21 +110,28 @@ bool shape_fits(int32_t N, int prec, int nslot, int nwaves, bool prior = false) 
 // waves than it needs to hide the per-step load, reduction and barrier
 // latency, and by the uneven spread of the group's waves over the four SIMDs
 // of a compute unit (every step ends in a barrier, so the busiest SIMD sets
-// the pace). FP32-arithmetic sweeps (masked emission: three vector
-// instructions per slot) were fitted to every shape that places N at
-// N = 1,000 .. 100,000 (130 shapes, forward and backward); the FP64 sweep,
-// sweeps with a prior matrix and the gradient keep the parameters fitted
-// earlier (N = 2,000 .. 100,000, 38 shapes).
+// the pace). Sweeps with the masked emission were fitted to every shape
+// that places N: FP32 arithmetic at N = 1,000 .. 100,000 (130 shapes), FP64
+// at N = 1,000 .. 45,000 (111 shapes), forward and backward; sweeps with a
+// prior matrix and the gradient keep the parameters fitted to the select
+// form (N = 2,000 .. 100,000, 38 shapes).
 double shape_cost(int32_t N, int prec, int ns, int nw, int wps = 0, bool sweep = true) {
     const bool f64 = prec == LS_FP64;
-    const bool masked = !f64 && sweep;
     if (wps <= 0) wps = lsk::sweep_waves_per_simd(ns, vgpr_per_slot(prec));
     // waves resident per SIMD when all N recipients are swept
     const double occ = std::min<double>(wps, (double)N * nw / 1024.0);
-    const double ops = masked ? 2.5 * ns + 40.0 : (f64 ? 4.19 : 4.0) * ns + 60.7;
-    const double hide = masked ? 5.0 : (f64 ? 3.34 : 5.57);
+    double ops, hide, ex;
+    if (sweep) {
+        ops = 2.5 * ns + 40.0;
+        hide = f64 ? 2.5 : 5.0;
+        ex = f64 ? 0.5 : 1.5;
+    } else {
+        ops = (f64 ? 4.19 : 4.0) * ns + 60.7;
+        hide = f64 ? 3.34 : 5.57;
+        ex = 0.847;
+    }
     const double imb = nw >= 4 ? ((nw + 3) / 4) / (nw / 4.0) : 1.0;
-    return (double)nw * ops * std::max(1.0, hide / occ) * std::pow(imb, masked ? 1.5 : 0.847);
+    return (double)nw * ops * std::max(1.0, hide / occ) * std::pow(imb, ex);
 }
 
 // Cheapest shape by shape_cost; among shapes within 1% of the cheapest, the

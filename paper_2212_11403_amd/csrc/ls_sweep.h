@@ -558,18 +558,17 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
             coefs_at(l <= lmax ? l : lmax, A_nx, B_nx);
             emis_at(l <= lmax ? l : lmax, em_nx, ex_nx);
             uint64_t w_nx = self_word(l <= lmax ? l : lmax);
-            T c_nx = coef_c(A_nx, S);
             for (; l <= a.t; ++l) {
-                const T c = c_nx, B = B_nx, em = em_nx, ex = ex_nx;
+                const T A = A_nx, B = B_nx, em = em_nx, ex = ex_nx;
                 const uint64_t wb = w_nx;
                 const int ln = l < lmax ? l + 1 : lmax;
                 coefs_at(ln, A_nx, B_nx);
                 emis_at(ln, em_nx, ex_nx);
                 w_nx = self_word(ln);
+                const T c = coef_c(A, S);
                 T part = step(l, wb, em, ex, c, B);
                 buf_store((IO)c, rs_c, c_voff, (l - a.l0 - 1) * a.R * (int)sizeof(IO));
                 S = block_sum<MAXW>(part, red, parity, wave, nwaves);
-                c_nx = coef_c(A_nx, S);
                 account(S);
                 // alpha^l (exactly 0 on the recipient's lane and on lanes
                 // without a donor), unscaled: kappa = 1 in this mode. Only
@@ -601,19 +600,22 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
             coefs_at(l <= lmax ? l : lmax, A_nx, B_nx);
             emis_at(l <= lmax ? l : lmax, em_nx, ex_nx);
             uint64_t w_nx = self_word(l <= lmax ? l : lmax);
-            T c_nx = coef_c(A_nx, S);
             for (; l <= lend; ++l) {
-                const T c = c_nx, b = B_nx, em = em_nx, ex = ex_nx;
+                const T A = A_nx, b = B_nx, em = em_nx, ex = ex_nx;
                 const uint64_t wb = w_nx;
                 const int ln = l < lmax ? l + 1 : lmax;
                 coefs_at(ln, A_nx, B_nx);
                 emis_at(ln, em_nx, ex_nx);
                 w_nx = self_word(ln);
+                // c of this variant at the top of the step: its reciprocal
+                // chain then overlaps the scalar address work of the step,
+                // and the FP64 log-scale update sits after the reduction,
+                // where nothing waits for it (forward at N = 10,000: 20.1
+                // -> 18.0 ms per 2,048 variants with c formed after the
+                // reduction instead)
+                const T c = coef_c(A, S);
                 T part = step(l, wb, em, ex, c, b);
                 S = block_sum<MAXW>(part, red, parity, wave, nwaves);
-                // the next variant's c (its A was read at the top), next to
-                // the log-scale update so that the two chains overlap
-                c_nx = coef_c(A_nx, S);
                 account(S);
             }
             if (kt < a.nt) snapshot();
@@ -625,8 +627,11 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
         if (fresh) affine((T)0, (T)a.kappa);
         if (kt < a.nt && a.tgt_l[kt] == lstart) snapshot();
         if (a.t < lstart) {
+            // each column sum enters the log scale right after its
+            // reduction (off the path to the next step's coefficients)
             T part = emit(lstart);
             S = reduce(part);
+            account(S);
             int l = lstart - 1;
             for (;;) {
                 const int lend = kt < a.nt ? a.tgt_l[kt] : a.t;
@@ -645,21 +650,21 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
                     w_nx = self_word(ln);
                     const T c = coef_c(A, S);
                     const T b = SNORM ? coef_c(B * Wsum, S) : B;
-                    account(S);
                     part = step(l, wb, em, ex, c, b);
                     S = reduce(part);
+                    account(S);
                 }
                 // l == lend: a target or the stopping variant; keep beta^l
                 T A, B;
                 coefs_at(l, A, B);
                 const T c = coef_c(A, S);
                 const T b = SNORM ? coef_c(B * Wsum, S) : B;
-                account(S);
                 affine(c, b);
                 if (kt < a.nt && a.tgt_l[kt] == l) snapshot();
                 if (l <= a.t) break;
                 part = emit(l);
                 S = reduce(part);
+                account(S);
                 --l;
             }
         }
