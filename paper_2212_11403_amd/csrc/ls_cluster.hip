@@ -18,6 +18,7 @@
 // are rescanned; every other row only compares its new distance to a.
 #include <math.h>
 
+#include <cstdlib>
 #include <mutex>
 
 #include "ls_cluster.h"
@@ -129,27 +130,54 @@ linkage_init_kernel(const T *__restrict__ D, int32_t N, int32_t T_, size_t ws_st
     }
 }
 
-// All N-1 merges of matrix blockIdx.x, then its leaf order.
-template <class T>
+// Bytes of local memory the merge kernel keeps nn, nd and the occupancy
+// flags of one matrix in (the rest of its state stays in the workspace).
+__host__ __device__ constexpr size_t linkage_lds_bytes(int32_t N, size_t tsize) {
+    return 16 * (((size_t)N * 4 + 15) / 16) + 16 * (((size_t)N * tsize + 15) / 16) + (size_t)N;
+}
+
+// All N-1 merges of matrix blockIdx.x, then its leaf order. With SMEM the
+// per-slot state every merge scans (nearest slot, its distance, occupancy)
+// lives in local memory (linkage_lds_bytes), copied from the workspace the
+// first pass filled; the candidate search then reads no global memory.
+template <class T, bool SMEM>
 __global__ void __launch_bounds__(1024)
 linkage_kernel(T *__restrict__ D, int32_t N, size_t ws_stride, char *ws, double *__restrict__ Z,
                int32_t *__restrict__ order) {
 #pragma clang fp contract(off)
     __shared__ Cand<T> buf[16];
     __shared__ int nflag;
+    extern __shared__ __align__(16) char lds[];
     const int t = blockIdx.x;
     T *Dm = D + (int64_t)t * N * N;
     char *w = ws + (size_t)t * ws_stride;
     const size_t a4 = 256 * (((size_t)N * 4 + 255) / 256);
     const size_t aT = 256 * (((size_t)N * sizeof(T) + 255) / 256);
-    int32_t *nn = reinterpret_cast<int32_t *>(w);
-    T *nd = reinterpret_cast<T *>(w + a4);
     int32_t *size = reinterpret_cast<int32_t *>(w + a4 + aT);
     int32_t *id = reinterpret_cast<int32_t *>(w + 2 * a4 + aT);
     int32_t *flag = reinterpret_cast<int32_t *>(w + 3 * a4 + aT);
-    uint8_t *live = reinterpret_cast<uint8_t *>(w + 4 * a4 + aT);
-    double *Zm = Z + (int64_t)t * (N - 1) * 4;
+    int32_t *nn;
+    T *nd;
+    uint8_t *live;
     const int tid = threadIdx.x, nth = blockDim.x;
+    if constexpr (SMEM) {
+        const size_t s4 = 16 * (((size_t)N * 4 + 15) / 16);
+        const size_t sT = 16 * (((size_t)N * sizeof(T) + 15) / 16);
+        nn = reinterpret_cast<int32_t *>(lds);
+        nd = reinterpret_cast<T *>(lds + s4);
+        live = reinterpret_cast<uint8_t *>(lds + s4 + sT);
+        const int32_t *gnn = reinterpret_cast<const int32_t *>(w);
+        const T *gnd = reinterpret_cast<const T *>(w + a4);
+        for (int k = tid; k < N; k += nth) {
+            nn[k] = gnn[k];
+            nd[k] = gnd[k];
+        }
+    } else {
+        nn = reinterpret_cast<int32_t *>(w);
+        nd = reinterpret_cast<T *>(w + a4);
+        live = reinterpret_cast<uint8_t *>(w + 4 * a4 + aT);
+    }
+    double *Zm = Z + (int64_t)t * (N - 1) * 4;
     for (int k = tid; k < N; k += nth) {
         size[k] = 1;
         id[k] = k;
@@ -256,28 +284,69 @@ size_t linkage_workspace_bytes(int32_t N, int32_t T, int is_f64) {
     return (size_t)T * (4 * a4 + aT + a1);
 }
 
-hipError_t launch_linkage(void *D, int32_t N, int32_t T, int is_f64, double *Z, int32_t *order,
-                          void *ws, hipStream_t st) {
-    if (N < 1 || T < 1) return hipSuccess;
-    const size_t stride = linkage_workspace_bytes(N, 1, is_f64);
-    char *w = static_cast<char *>(ws);
-    const int64_t rows = (int64_t)N * T;
+namespace {
+
+// Local memory a workgroup may allocate on the current device (0 if the
+// runtime does not say), asked once per device.
+size_t max_group_lds() {
+    static std::mutex mu;
+    static int known[64] = {};
+    static size_t bytes[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!known[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            v = 0;
+        bytes[dev] = v > 0 ? (size_t)v : 0;
+        known[dev] = 1;
+    }
+    return bytes[dev];
+}
+
+template <class T>
+hipError_t launch_linkage_t(T *D, int32_t N, int32_t T_, double *Z, int32_t *order, char *w,
+                            hipStream_t st) {
+    const size_t stride = linkage_workspace_bytes(N, 1, sizeof(T) == 8);
+    const int64_t rows = (int64_t)N * T_;
     const int64_t blocks = (rows + 3) / 4;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    if (is_f64) {
-        if (N > 1)
-            hipLaunchKernelGGL(linkage_init_kernel<double>, dim3((unsigned)blocks), dim3(256), 0,
-                               st, (const double *)D, N, T, stride, w);
-        hipLaunchKernelGGL(linkage_kernel<double>, dim3(T), dim3(1024), 0, st, (double *)D, N,
+    if (N > 1)
+        hipLaunchKernelGGL(linkage_init_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st,
+                           (const T *)D, N, T_, stride, w);
+    // threads per merge workgroup: 1024, or LS_LINKAGE_THREADS (a multiple
+    // of 64 up to 1024)
+    int threads = 1024;
+    if (const char *env = std::getenv("LS_LINKAGE_THREADS")) {
+        const int v = std::atoi(env);
+        if (v >= 64 && v <= 1024 && v % 64 == 0) threads = v;
+    }
+    // the static part of the kernel's local memory: 16 candidates and a count
+    const size_t lds = linkage_lds_bytes(N, sizeof(T));
+    const size_t fixed = 16 * sizeof(Cand<T>) + 64;
+    if (lds + fixed <= max_group_lds()) {
+        hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&linkage_kernel<T, true>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((linkage_kernel<T, true>), dim3(T_), dim3(threads), lds, st, D, N,
                            stride, w, Z, order);
     } else {
-        if (N > 1)
-            hipLaunchKernelGGL(linkage_init_kernel<float>, dim3((unsigned)blocks), dim3(256), 0,
-                               st, (const float *)D, N, T, stride, w);
-        hipLaunchKernelGGL(linkage_kernel<float>, dim3(T), dim3(1024), 0, st, (float *)D, N,
+        hipLaunchKernelGGL((linkage_kernel<T, false>), dim3(T_), dim3(threads), 0, st, D, N,
                            stride, w, Z, order);
     }
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_linkage(void *D, int32_t N, int32_t T, int is_f64, double *Z, int32_t *order,
+                          void *ws, hipStream_t st) {
+    if (N < 1 || T < 1) return hipSuccess;
+    char *w = static_cast<char *>(ws);
+    if (is_f64) return launch_linkage_t<double>((double *)D, N, T, Z, order, w, st);
+    return launch_linkage_t<float>((float *)D, N, T, Z, order, w, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -116,6 +116,33 @@ def test_benchmark_workload_distance_matrices(ls):
         assert np.array_equal(order[t], orr), t
 
 
+def test_state_in_global_memory(ls):
+    """A matrix whose per-slot state does not fit a workgroup's local memory
+    (FP64, N = 13,000: 13 bytes per slot) runs the merge kernel with that
+    state in the workspace; merges and order equal the oracle's."""
+    from scipy.spatial.distance import cdist
+    rng = np.random.default_rng(13)
+    X = rng.random((13_000, 3))
+    D = cdist(X, X)
+    Z, order = _gpu_linkage(ls, [D], np.float64)
+    Zr, orr = oracle.average_linkage(D)
+    assert np.array_equal(Z[0], Zr)
+    assert np.array_equal(order[0], orr)
+
+
+def test_smaller_workgroups(ls, monkeypatch):
+    """The merge kernel at 256 and 64 threads per matrix (LS_LINKAGE_THREADS)
+    gives the same merges as the oracle."""
+    mats = [_points(700, 21, np.float32), _ties(700, 22, np.float32, 8)]
+    for th in ("256", "64"):
+        monkeypatch.setenv("LS_LINKAGE_THREADS", th)
+        Z, order = _gpu_linkage(ls, mats, np.float32)
+        for t, D in enumerate(mats):
+            Zr, orr = oracle.average_linkage(D)
+            assert np.array_equal(Z[t], Zr), (th, t)
+            assert np.array_equal(order[t], orr), (th, t)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_standardised_rows_vs_oracle(ls, prec):
     """Half-distance rows of the small workload standardised in place, in the
