@@ -161,6 +161,10 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
     // the emission pair (match, mismatch), formed in FP64 by the host and
     // rounded once to the sweep precision
     const T th_m = (T)a.th_match, th_x = (T)a.th_mis;
+    // masked emission with a scalar mu: the scaled member is fixed for the
+    // whole sweep and held in a vector register
+    T r_fix = (T)0;
+    if constexpr (XMUL && !MUV && DIR == 1) r_fix = in_vgpr(th_m != (T)1 ? th_m : th_x);
     // with a prior matrix: pi' = (N-1) Pi_ji per slot, 0 on the recipient's
     // lane and on lanes without a donor
     T pv[PI ? NSLOT : 1];
@@ -278,6 +282,14 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
             for (int s = 0; s < NSLOT; ++s) v[s] = (T)(ST)v[s];
         }
     };
+    // x on the lanes that hold a donor other than the recipient, 0 elsewhere
+    // (slot 0 and the special slots). Their entries are 0 and stay 0, so
+    // c v + b followed by this multiply gives the bits c v + 0 gives.
+    auto keep_lanes = [&](int s, T x) __attribute__((always_inline)) -> T {
+        if (s == 0 && NR > 0) return x * keep0;
+        if (s >= NR) return x * spec_keep[s - NR];
+        return x;
+    };
     // Row words of slot s at variant row `row`.
     auto mask_of = [&](const uint64_t *row, int s) __attribute__((always_inline)) -> uint64_t {
         return (s < NR) ? row[reg_base + s] : row[spec_off[s - NR]];
@@ -291,16 +303,18 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
     auto xmul_params = [&](uint64_t sw_bits, T em, T ex, T &r, uint64_t &flip)
                            __attribute__((always_inline)) {
         const bool rb = (sw_bits & self_bit) != 0;
-        T m1, x1;
+        T m1;
         if constexpr (MUV) {
             m1 = em;
-            x1 = ex;
+            r = in_vgpr(em != (T)1 ? em : ex);
+        } else if constexpr (DIR == 1) {
+            m1 = th_m;
+            r = r_fix;
         } else {
             m1 = th_m;
-            x1 = th_x;
+            r = in_vgpr(th_m != (T)1 ? th_m : th_x);
         }
         const bool on_match = m1 != (T)1;
-        r = in_vgpr(on_match ? m1 : x1);
         // a float compare runs on the vector unit; the flag goes back to a
         // scalar register, which the EXEC arithmetic needs
         flip = uniform((int)(rb != on_match)) ? ~0ull : 0ull;
@@ -321,10 +335,17 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
             xmul_params(sw_bits, em, ex, r, flip);
 #pragma unroll
             for (int s = 0; s < NSLOT; ++s) {
-                T bb;
-                if constexpr (PI && DIR == 0) bb = b * pv[s];
-                else bb = (s < NR) ? (s == 0 ? b * keep0 : b) : b * spec_keep[s - NR];
-                v[s] = fma(c, (T)v[s], bb);
+                if constexpr (PI && DIR == 0) {
+                    v[s] = fma(c, (T)v[s], b * pv[s]);
+                } else if constexpr (DIR == 1) {
+                    v[s] = keep_lanes(s, fma(c, (T)v[s], b));
+                } else {
+                    // the forward keeps the rho-term multiplier inside: with
+                    // it outside, the scheduler issued the row loads after
+                    // this block (forward at N = 10,000: 4% slower)
+                    const T bb = (s < NR) ? (s == 0 ? b * keep0 : b) : b * spec_keep[s - NR];
+                    v[s] = fma(c, (T)v[s], bb);
+                }
             }
             // FP16 storage rounds what a table holds: the backward vector
             // kappa beta^l before its emission, the forward kappa alpha^l
@@ -352,12 +373,8 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
     };
     // v <- c v + b (no emission): the backward vector before theta^l
     auto affine = [&](T c, T b) __attribute__((always_inline)) {
-        const T b0 = b * keep0;
 #pragma unroll
-        for (int s = 0; s < NSLOT; ++s) {
-            const T bb = (s < NR) ? (s == 0 ? b0 : b) : b * spec_keep[s - NR];
-            v[s] = fma(c, v[s], bb);
-        }
+        for (int s = 0; s < NSLOT; ++s) v[s] = keep_lanes(s, fma(c, v[s], b));
         quantise();
     };
     // v <- theta^l (.) v; returns this lane's partial sum
