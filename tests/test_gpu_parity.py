@@ -190,9 +190,11 @@ def test_forced_shapes_fp64(ls, N, ns, nw):
 
 WIDE_SHAPES = [  # (precision, N, slots, waves): groups of 5..12 waves with wide slots, where
     # the cross-wave sum covers 8 or 12 lanes (the register budget of the slot
-    # count caps the group at 8 or 12 waves)
+    # count caps the group at 8 or 12 waves); 128 and 132 slots in 12-wave groups
+    # run three waves per SIMD
     ("fp64", 20000, 56, 6), ("fp64", 40000, 80, 8), ("fp64", 26000, 40, 11),
     ("fp32", 54000, 172, 5), ("fp32", 100000, 196, 8), ("fp32", 58000, 104, 9),
+    ("fp32", 100000, 132, 12), ("fp32", 98000, 128, 12),
 ]
 
 
