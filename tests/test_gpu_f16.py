@@ -12,7 +12,7 @@ import pytest
 import oracle
 from lsinputs import make_inputs, pack_haplotypes, rho_from_spacings
 
-from _gpu import F32_POST_ATOL, check_reduced, need_gpu
+from _gpu import F32_POST_ATOL, check_reduced, forced_shape, need_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -144,3 +144,32 @@ def test_skewed_prior_stays_in_range(ls, skew):
     ls.posterior_distance(fwd, bck, m, P, None)
     assert torch.isfinite(P).all()
     check_reduced("f16", _np(P), ref["P"][1], "prob")
+
+
+@pytest.mark.parametrize("shape", [None, (196, 8)])
+def test_widest_groups_at_full_size(ls, shape):
+    """N = 100,000 with FP16 storage, in the 132-slot 12-wave groups the
+    shape choice takes there (three waves per SIMD) and in the 196 x 8
+    groups: posteriors and log-likelihoods within the FP16 bounds of the
+    oracle on seeded recipients at both ends and in the middle."""
+    N, L = 100_000, 9
+    rng = np.random.default_rng(100)
+    F = (rng.random((L, 6)) < 0.4).astype(np.uint8)
+    h = F[np.arange(L)[:, None], rng.integers(0, 6, size=(L, N))]
+    h = (h ^ (rng.random((L, N)) < 0.01)).astype(np.uint8)
+    H = pack_haplotypes(h)
+    rho = rho_from_spacings(rng.exponential(0.05, L - 1))
+    mu = 0.01
+    targets = np.array([2, 6], np.int32)
+    rec = np.array([0, 1, 63, 64, N // 2, N - 2, N - 1], dtype=np.int32)
+    ref = oracle.run_pass(H, N, L, rho, mu, rec, targets, want=("P",))
+    m = ls.Model(H, N, rho, mu)
+    if shape is None:
+        assert ls.kernel_shape(N, "f16") == (132, 12)
+        r = ls.decode(m, targets, "f16", recipients=rec, want=("P",))
+    else:
+        with forced_shape(*shape):
+            assert ls.kernel_shape(N, "f16") == shape
+            r = ls.decode(m, targets, "f16", recipients=rec, want=("P",))
+    check_reduced("f16", _np(r["P"]), ref["P"], "prob")
+    check_reduced("f16", _np(r["fwd"].log_scale), ref["llf"], "log")
