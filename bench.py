@@ -262,10 +262,10 @@ def gradient_workload(ls, torch, oracle, nthreads, reps=3):
 
 def precision_workload(ls, torch, oracle, nthreads, count=64, timed_recipients=2560):
     """The precision study (N = 50,000, L = 20,000, rare-variant mosaic, 20
-    targets): FP32 and FP16-stored vectors against the FP64 oracle on
-    `count` seeded recipients (posteriors at every target, log-likelihoods;
-    the FP64 GPU path does not fit one compute unit at this N), and the
-    forward+backward cell rate of both on `timed_recipients` recipients."""
+    targets): FP32, FP16-stored and FP64 vectors against the FP64 oracle on
+    `count` seeded recipients (posteriors at every target, log-likelihoods),
+    and the forward+backward cell rate of each on `timed_recipients`
+    recipients."""
     from lsinputs import make_inputs, seeded_recipients
     t0 = time.time()
     x = make_inputs("c3")
@@ -281,7 +281,7 @@ def precision_workload(ls, torch, oracle, nthreads, count=64, timed_recipients=2
            "oracle_sample": f"{len(rec)} seeded recipients, all donors, all variants, all targets",
            "oracle_seconds": time.perf_counter() - t0}
     trec = np.arange(min(timed_recipients, N), dtype=np.int32)
-    for prec in ("fp32", "f16"):
+    for prec in ("fp32", "f16", "fp64"):
         r = ls.decode(m, targets, prec, recipients=rec, want=("P",))
         P = r["P"].double().cpu().numpy()
         ll = r["fwd"].log_scale.cpu().numpy()

@@ -98,7 +98,7 @@ std::vector<int> menu(int prec, bool grad = false) {
 bool shape_fits(int32_t N, int prec, int nslot, int nwaves, bool prior = false) {
     if (!in_menu(prec, nslot)) return false;
     const int vps = lsk::sweep_slot_vgprs(vgpr_per_slot(prec), prior);
-    if (nwaves < 1 || nwaves > lsk::max_waves_for(nslot, vps)) return false;
+    if (nwaves < 1 || nwaves > lsk::max_waves_for(nslot, vps, prior)) return false;
     const int NW = (N + 63) / 64, NF = N / 64;
     const int K = lsk::special_slots(nslot);
     return (int64_t)nwaves * (nslot - K) <= NF && (int64_t)nwaves * nslot >= NW;

@@ -9,7 +9,8 @@ static hipError_t launch_every_one(const SweepPtrs &p, const SweepArgs &a, int n
                                    hipStream_t st) {
     using PT = PrecF64;
     const int vps = sweep_slot_vgprs(PT::vgpr_per_slot, p.prior != nullptr);
-    if (nwaves < 1 || nwaves > max_waves_for(NSLOT, vps)) return hipErrorInvalidValue;
+    if (nwaves < 1 || nwaves > max_waves_for(NSLOT, vps, p.prior != nullptr))
+        return hipErrorInvalidValue;
     if (a.nblk < 1 || a.r0 < 0 || a.r0 + a.nblk > a.R) return hipErrorInvalidValue;
     if (p.emis && p.prior)
         hipLaunchKernelGGL((sweep_kernel<PT, NSLOT, 0, true, true, true>), dim3(a.nblk),

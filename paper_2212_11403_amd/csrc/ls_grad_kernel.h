@@ -58,7 +58,7 @@ struct GradSegArgs {
 // with a 4-wave bound, but never launches it.)
 __host__ __device__ constexpr int grad_kernel_waves(int nslot, int vgpr_per_slot, bool narrow,
                                                     bool prior = false) {
-    return !narrow ? max_waves_for(nslot, sweep_slot_vgprs(vgpr_per_slot, prior))
+    return !narrow ? max_waves_for(nslot, sweep_slot_vgprs(vgpr_per_slot, prior), prior)
                    : (grad_max_waves(nslot, vgpr_per_slot, prior) > 0
                           ? grad_max_waves(nslot, vgpr_per_slot, prior)
                           : 4);
@@ -394,7 +394,7 @@ template <class PT, int NSLOT>
 constexpr bool grad_wide_needed() {
     constexpr int v = PT::vgpr_per_slot;
     return grad_max_waves(NSLOT, v) < max_waves_for(NSLOT, v) ||
-           grad_max_waves(NSLOT, v, true) < max_waves_for(NSLOT, sweep_slot_vgprs(v, true));
+           grad_max_waves(NSLOT, v, true) < max_waves_for(NSLOT, sweep_slot_vgprs(v, true), true);
 }
 
 // Adjoint launchers over the slot menu, one per precision and variant

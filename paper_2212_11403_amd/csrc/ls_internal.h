@@ -89,13 +89,18 @@ struct Shape {
 // with: the register file of one SIMD (512 VGPRs per lane) must hold every
 // wave the workgroup places on it. The constant covers the per-wave registers
 // besides the resident vector (emission pair, accumulators, special-slot
-// multipliers, the division and reduction temporaries); with one register per
+// multipliers, the division and reduction temporaries). With one register per
 // slot it is the allowance the compile budget gives (sweep_waves_per_simd),
 // which the widest kernels keep within (about 23 registers beside the slots
 // at 128..144 slots), so that 128 and 132 slots run 12-wave groups at three
-// waves per SIMD.
-__host__ __device__ constexpr int max_waves_for(int nslot, int vgpr_per_slot) {
-    int need = nslot * vgpr_per_slot + (vgpr_per_slot >= 2 ? 64 : 36);
+// waves per SIMD. FP64 sweeps without a prior column use about 33 beside
+// their two registers per slot (223..225 VGPRs at 96 slots); above 96 slots
+// they are allowed 48, which lets 100 and 104 slots run 8-wave groups at two
+// waves per SIMD (N up to 53,248 in FP64). Below that, and with a prior
+// column, the allowance stays 64.
+__host__ __device__ constexpr int max_waves_for(int nslot, int vgpr_per_slot, bool prior = false) {
+    const int allow = vgpr_per_slot == 1 ? 36 : (vgpr_per_slot == 2 && !prior && nslot > 96 ? 48 : 64);
+    int need = nslot * vgpr_per_slot + allow;
     need = (need + 7) / 8 * 8;
     int per_simd = 512 / need;
     if (per_simd > 8) per_simd = 8;
@@ -159,7 +164,7 @@ __host__ __device__ constexpr int sweep_budget_slots(int nslot, int vgpr_per_slo
     X(168) X(172) X(176) X(180) X(184) X(188) X(192) X(196) X(200)
 #define LS_MENU_F64(X) \
     X(1) X(2) X(3) X(4) X(8) X(12) X(16) X(20) X(24) X(28) X(32) X(40) X(48) X(56) X(64) \
-    X(68) X(72) X(76) X(80) X(84) X(88) X(92) X(96)
+    X(68) X(72) X(76) X(80) X(84) X(88) X(92) X(96) X(100) X(104)
 
 // Slot counts of the gradient kernel (two precisions).
 #define LS_MENU_GRAD(X) \

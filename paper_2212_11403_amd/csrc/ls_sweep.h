@@ -92,7 +92,7 @@ __device__ __forceinline__ SpecSlot special_slot(int q, int NF, int N, int g, bo
 // any prior; its log scale adds log(S / ((N-1) kappa)) per step, which keeps
 // the stored vector times exp(log scale) equal to kappa' beta^l G^l.
 template <class PT, int NSLOT, int DIR, bool EVERY = false, bool MUV = false, bool PI = false>
-__global__ void __launch_bounds__(64 * max_waves_for(NSLOT, sweep_slot_vgprs(PT::vgpr_per_slot, PI)))
+__global__ void __launch_bounds__(64 * max_waves_for(NSLOT, sweep_slot_vgprs(PT::vgpr_per_slot, PI), PI))
 __attribute__((amdgpu_waves_per_eu(
     sweep_waves_per_simd(sweep_budget_slots(NSLOT, sweep_slot_vgprs(PT::vgpr_per_slot, PI), EVERY),
                          sweep_slot_vgprs(PT::vgpr_per_slot, PI)))))
@@ -111,7 +111,7 @@ sweep_kernel(const uint64_t *__restrict__ Hr, const typename PT::T *__restrict__
     using IO = typename PT::IO;
     constexpr int K = special_slots(NSLOT);
     constexpr int NR = NSLOT - K;
-    constexpr int MAXW = max_waves_for(NSLOT, sweep_slot_vgprs(PT::vgpr_per_slot, PI));
+    constexpr int MAXW = max_waves_for(NSLOT, sweep_slot_vgprs(PT::vgpr_per_slot, PI), PI);
     // emission as a lane-masked multiply (every sweep whose emission pairs
     // have a member equal to 1: all but FP64 with a per-variant mu), except
     // the gradient's keep-alpha recompute, where the select form measured

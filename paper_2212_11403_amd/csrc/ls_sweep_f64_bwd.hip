@@ -7,7 +7,8 @@ template <int NSLOT>
 static hipError_t launch_one(const SweepPtrs &p, const SweepArgs &a, int nwaves, hipStream_t st) {
     using PT = PrecF64;
     const int vps = sweep_slot_vgprs(PT::vgpr_per_slot, p.prior != nullptr);
-    if (nwaves < 1 || nwaves > max_waves_for(NSLOT, vps)) return hipErrorInvalidValue;
+    if (nwaves < 1 || nwaves > max_waves_for(NSLOT, vps, p.prior != nullptr))
+        return hipErrorInvalidValue;
     if (a.nblk < 1 || a.r0 < 0 || a.r0 + a.nblk > a.R) return hipErrorInvalidValue;
     if (p.prior && p.emis)
         hipLaunchKernelGGL((sweep_kernel<PT, NSLOT, 1, false, true, true>), dim3(a.nblk),
